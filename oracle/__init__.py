@@ -1,0 +1,269 @@
+"""FP64 CPU oracle for u ubar -> n photons (arXiv:0908.4403) -- TEST INFRASTRUCTURE.
+
+Only tests/, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the HIP library
+in ``paper_0908_4403_amd``; the arithmetic lives in ``heget_oracle.c`` (plain C,
+FP64), this module only marshals numpy arrays through ctypes.
+
+Event layout everywhere: ``p[n+2, 4]`` with rows u (+z), ubar (-z), photons;
+columns (E, px, py, pz) in GeV.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+_u32p = C.POINTER(C.c_uint32)
+
+
+class OrcConfig(C.Structure):
+    _fields_ = [("mode", C.c_int), ("seed", C.c_uint64), ("npoints", C.c_int64),
+                ("first_point", C.c_int64), ("sqrt_s", C.c_double),
+                ("sqrt_shat_lo", C.c_double), ("sqrt_shat_hi", C.c_double),
+                ("pt_min", C.c_double), ("eta_max", C.c_double), ("dr_min", C.c_double),
+                ("alpha", C.c_double), ("charge", C.c_double)]
+
+
+class OrcResult(C.Structure):
+    _fields_ = [("sigma_fb", C.c_double), ("err_fb", C.c_double), ("sum_w", C.c_double),
+                ("sum_w_comp", C.c_double), ("sum_w2", C.c_double),
+                ("n_gen", C.c_int64), ("n_acc", C.c_int64)]
+
+
+FIXED_SHAT, UNIFORM_SQRTSHAT, PP_TOY = 0, 1, 2
+ALPHA = 1.0 / 137.0
+CHARGE_U = 2.0 / 3.0
+
+
+def lib():
+    """Load liboracle.so, compiling it first if it is not there."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.orc_uniform_pair.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, _dp]
+        L.orc_rambo.argtypes = [C.c_int, C.c_double, _dp, _dp]
+        L.orc_rambo_weight.argtypes = [C.c_int, C.c_double]
+        L.orc_rambo_weight.restype = C.c_double
+        L.orc_cm_event.argtypes = [C.c_int, C.c_double, C.c_uint64, C.c_uint64, _dp]
+        L.orc_cm_events.argtypes = [C.c_int, C.c_double, C.c_uint64, C.c_uint64, C.c_int64, _dp]
+        L.orc_pass_cuts.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_pass_cuts.restype = C.c_int
+        L.orc_amp.argtypes = [C.c_int, _dp, C.c_int, C.c_int, _ip, C.c_double, C.c_int, _dp, _dp]
+        L.orc_amp_from_u.argtypes = [C.c_int, _dp, C.c_int, C.c_int, _ip, C.c_double, _dp, _dp]
+        L.orc_amp_custom_eps.argtypes = [C.c_int, _dp, C.c_int, C.c_int, _dp, C.c_double,
+                                         _dp, _dp, _dp]
+        L.orc_amp_meet.argtypes = [C.c_int, _dp, C.c_int, C.c_int, _ip, C.c_double, C.c_int,
+                                   _dp, _dp]
+        L.orc_me2.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, C.c_int]
+        L.orc_me2.restype = C.c_double
+        L.orc_me2_batch.argtypes = [C.c_int, C.c_int64, _dp, C.c_double, C.c_double, _dp]
+        L.orc_me2_batch.restype = C.c_int
+        L.orc_me2_subsets.argtypes = [C.c_int, _dp, C.c_double, C.c_double]
+        L.orc_me2_subsets.restype = C.c_double
+        L.orc_me2_subsets_batch.argtypes = [C.c_int, C.c_int64, _dp, C.c_double, C.c_double, _dp]
+        L.orc_me2_subsets_batch.restype = C.c_int
+        L.orc_point.argtypes = [C.c_int, C.POINTER(OrcConfig), C.c_uint64, _dp, _dp, _dp, _dp]
+        L.orc_point.restype = C.c_int
+        L.orc_xsec.argtypes = [C.c_int, C.POINTER(OrcConfig), C.POINTER(OrcResult), _dp]
+        L.orc_xsec.restype = C.c_int
+        L.orc_gev2_fb.restype = C.c_double
+        _LIB = L
+    return _LIB
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def coupling(alpha: float = ALPHA, charge: float = CHARGE_U) -> float:
+    """gal[0] = gal[1] = -e Q with e = sqrt(4 pi alpha) (Appendix B.3.1)."""
+    return -np.sqrt(4.0 * np.pi * alpha) * charge
+
+
+# ---- random numbers and phase space ---------------------------------------
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(c.ctypes.data_as(_u32p), k.ctypes.data_as(_u32p),
+                            out.ctypes.data_as(_u32p))
+    return out
+
+
+def uniform_pair(seed: int, point: int, block: int, stream: int) -> np.ndarray:
+    u = np.zeros(2)
+    lib().orc_uniform_pair(seed, point, block, stream, _ptr(u))
+    return u
+
+
+def rambo(n: int, sqrt_s: float, u) -> np.ndarray:
+    u = _f64(u)
+    assert u.size == 4 * n
+    k = np.zeros((n, 4))
+    lib().orc_rambo(n, sqrt_s, _ptr(u), _ptr(k))
+    return k
+
+
+def rambo_weight(n: int, s: float) -> float:
+    return lib().orc_rambo_weight(n, s)
+
+
+def cm_event(n: int, sqrt_shat: float, seed: int, point: int) -> np.ndarray:
+    p = np.zeros((n + 2, 4))
+    lib().orc_cm_event(n, sqrt_shat, seed, point, _ptr(p))
+    return p
+
+
+def cm_events(n: int, sqrt_shat: float, seed: int, first: int, npoints: int) -> np.ndarray:
+    p = np.zeros((npoints, n + 2, 4))
+    lib().orc_cm_events(n, sqrt_shat, seed, first, npoints, _ptr(p))
+    return p
+
+
+def pass_cuts(k, y: float = 0.0, pt_min: float = 20.0, eta_max: float = 2.5,
+              dr_min: float = 0.4) -> bool:
+    k = _f64(k)
+    return bool(lib().orc_pass_cuts(k.shape[0], _ptr(k), y, pt_min, eta_max, dr_min))
+
+
+# ---- amplitudes -------------------------------------------------------------
+
+def _lam(lam):
+    a = np.ascontiguousarray(lam, dtype=np.int32)
+    return a, a.ctypes.data_as(_ip)
+
+
+def amp(p, h1: int, h2: int, lam, g: float | None = None, u_along_minus_z: bool = False) -> complex:
+    p = _f64(p)
+    n = p.shape[0] - 2
+    la, lp = _lam(lam)
+    re, im = C.c_double(), C.c_double()
+    lib().orc_amp(n, _ptr(p), h1, h2, lp, coupling() if g is None else g,
+                  int(u_along_minus_z), C.byref(re), C.byref(im))
+    return complex(re.value, im.value)
+
+
+def amp_from_u(p, h1: int, h2: int, lam, g: float | None = None) -> complex:
+    p = _f64(p)
+    n = p.shape[0] - 2
+    la, lp = _lam(lam)
+    re, im = C.c_double(), C.c_double()
+    lib().orc_amp_from_u(n, _ptr(p), h1, h2, lp, coupling() if g is None else g,
+                         C.byref(re), C.byref(im))
+    return complex(re.value, im.value)
+
+
+def amp_meet(p, h1: int, h2: int, lam, split: int = -1, g: float | None = None) -> complex:
+    p = _f64(p)
+    n = p.shape[0] - 2
+    la, lp = _lam(lam)
+    re, im = C.c_double(), C.c_double()
+    lib().orc_amp_meet(n, _ptr(p), h1, h2, lp, coupling() if g is None else g, split,
+                       C.byref(re), C.byref(im))
+    return complex(re.value, im.value)
+
+
+def amp_custom_eps(p, h1: int, h2: int, eps, g: float | None = None):
+    """Ordering sum with polarisation vectors eps[n,4] (complex); returns (amp, sum|diagrams|)."""
+    p = _f64(p)
+    n = p.shape[0] - 2
+    e = np.asarray(eps, dtype=np.complex128).reshape(n, 4)
+    flat = np.ascontiguousarray(np.stack([e.real, e.imag], axis=-1), dtype=np.float64)
+    re, im, sa = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_amp_custom_eps(n, _ptr(p), h1, h2, _ptr(flat), coupling() if g is None else g,
+                             C.byref(re), C.byref(im), C.byref(sa))
+    return complex(re.value, im.value), sa.value
+
+
+def me2(p, alpha: float = ALPHA, charge: float = CHARGE_U, skip_zero: bool = True,
+        u_along_minus_z: bool = False) -> float:
+    p = _f64(p)
+    return lib().orc_me2(p.shape[0] - 2, _ptr(p), alpha, charge, int(skip_zero),
+                         int(u_along_minus_z))
+
+
+def me2_batch(p_aos, alpha: float = ALPHA, charge: float = CHARGE_U):
+    """Returns (me2[np], threads used)."""
+    p = _f64(p_aos)
+    npts, n = p.shape[0], p.shape[1] - 2
+    out = np.zeros(npts)
+    t = lib().orc_me2_batch(n, npts, _ptr(p), alpha, charge, _ptr(out))
+    return out, t
+
+
+def me2_subsets(p, alpha: float = ALPHA, charge: float = CHARGE_U) -> float:
+    p = _f64(p)
+    return lib().orc_me2_subsets(p.shape[0] - 2, _ptr(p), alpha, charge)
+
+
+def me2_subsets_batch(p_aos, alpha: float = ALPHA, charge: float = CHARGE_U):
+    p = _f64(p_aos)
+    npts, n = p.shape[0], p.shape[1] - 2
+    out = np.zeros(npts)
+    t = lib().orc_me2_subsets_batch(n, npts, _ptr(p), alpha, charge, _ptr(out))
+    return out, t
+
+
+# ---- cross section ----------------------------------------------------------
+
+@dataclass
+class Config:
+    mode: int = FIXED_SHAT
+    seed: int = 0
+    npoints: int = 1024
+    first_point: int = 0
+    sqrt_s: float = 500.0
+    sqrt_shat_lo: float = 0.0
+    sqrt_shat_hi: float = 0.0
+    pt_min: float = 20.0
+    eta_max: float = 2.5
+    dr_min: float = 0.4
+    alpha: float = ALPHA
+    charge: float = CHARGE_U
+
+    def c(self) -> OrcConfig:
+        return OrcConfig(self.mode, self.seed, self.npoints, self.first_point, self.sqrt_s,
+                         self.sqrt_shat_lo, self.sqrt_shat_hi, self.pt_min, self.eta_max,
+                         self.dr_min, self.alpha, self.charge)
+
+
+def point(n: int, cfg: Config, i: int):
+    """(accepted, p[n+2,4] CM event, y, me2, w) of point i."""
+    p = np.zeros((n + 2, 4))
+    y, m, w = C.c_double(), C.c_double(), C.c_double()
+    c = cfg.c()
+    acc = lib().orc_point(n, C.byref(c), i, _ptr(p), C.byref(y), C.byref(m), C.byref(w))
+    return bool(acc), p, y.value, m.value, w.value
+
+
+def xsec(n: int, cfg: Config, want_weights: bool = False):
+    """dict(sigma_fb, err_fb, sum_w, sum_w_comp, sum_w2, n_gen, n_acc, threads[, w])."""
+    c = cfg.c()
+    r = OrcResult()
+    w = np.zeros(max(cfg.npoints, 1))
+    t = lib().orc_xsec(n, C.byref(c), C.byref(r), _ptr(w))
+    out = {f: getattr(r, f) for f, _ in OrcResult._fields_}
+    out["threads"] = t
+    if want_weights:
+        out["w"] = w[:cfg.npoints]
+    return out
+
+
+def gev2_fb() -> float:
+    return lib().orc_gev2_fb()

@@ -1,0 +1,694 @@
+/*
+ * FP64 CPU oracle for u ubar -> n gamma (arXiv:0908.4403).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by tests/, the smoke check and the
+ * cpu_baseline leg of the benchmark; never by the product library.
+ *
+ * Written from the definitions, not from the printed CUDA listings: the
+ * vertex functions are products of explicit 4x4 Dirac matrices in the chiral
+ * representation that the HELAS conventions of Appendix B use, the amplitude
+ * is the plain sum over all n! orderings of eq. (6)-(8), and the cross
+ * section is eq. (1)-(2) summed point by point.  Slow on purpose.
+ */
+#define _GNU_SOURCE
+#include "heget_oracle.h"
+
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11): ten rounds of the 4x32 Philox S-box with         */
+/* multipliers 0xD2511F53, 0xCD9E8D57 and Weyl key increments 0x9E3779B9      */
+/* (golden ratio) and 0xBB67AE85 (sqrt(3)-1).                                 */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k0;
+        uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+    memcpy(out, c, sizeof c);
+}
+
+static double u53(uint32_t lo, uint32_t hi)
+{
+    uint64_t w = ((uint64_t)hi << 32) | lo;
+    return ((double)(w >> 11) + 0.5) * 0x1.0p-53;
+}
+
+void orc_uniform_pair(uint64_t seed, uint64_t point, uint32_t block, uint32_t stream,
+                      double u[2])
+{
+    uint32_t ctr[4] = {(uint32_t)point, (uint32_t)(point >> 32), block, stream};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    u[0] = u53(r[0], r[1]);
+    u[1] = u53(r[2], r[3]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* RAMBO for massless momenta (Kleiss, Stirling, Ellis 1986).                */
+/* ------------------------------------------------------------------------ */
+void orc_rambo(int n, double sqrt_s, const double *u, double *k)
+{
+    double q[8][4];
+    double Q[4] = {0, 0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+        /* isotropic direction and energy density q0 exp(-q0) */
+        double c = 2.0 * u[4 * i + 0] - 1.0;
+        double s = sqrt(1.0 - c * c);
+        double f = 2.0 * M_PI * u[4 * i + 1];
+        double e = -log(u[4 * i + 2] * u[4 * i + 3]);
+        q[i][0] = e;
+        q[i][1] = e * s * cos(f);
+        q[i][2] = e * s * sin(f);
+        q[i][3] = e * c;
+        for (int m = 0; m < 4; ++m) Q[m] += q[i][m];
+    }
+    /* conformal transformation: boost to the rest frame of Q and rescale */
+    double M = sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
+    double b[3] = {-Q[1] / M, -Q[2] / M, -Q[3] / M};
+    double x = sqrt_s / M;
+    double gam = Q[0] / M;
+    double a = 1.0 / (1.0 + gam);
+    for (int i = 0; i < n; ++i) {
+        double bq = b[0] * q[i][1] + b[1] * q[i][2] + b[2] * q[i][3];
+        k[4 * i + 0] = x * (gam * q[i][0] + bq);
+        for (int m = 1; m < 4; ++m)
+            k[4 * i + m] = x * (q[i][m] + b[m - 1] * q[i][0] + a * bq * b[m - 1]);
+    }
+}
+
+/* Volume of the massless n-body phase space of eq. (4):
+ * (2 pi)^(4-3n) (pi/2)^(n-1) s^(n-2) / ((n-1)! (n-2)!). */
+double orc_rambo_weight(int n, double s)
+{
+    double fact_n1 = 1.0, fact_n2 = 1.0;
+    for (int i = 2; i <= n - 1; ++i) fact_n1 *= i;
+    for (int i = 2; i <= n - 2; ++i) fact_n2 *= i;
+    return pow(2.0 * M_PI, 4.0 - 3.0 * n) * pow(M_PI / 2.0, n - 1) * pow(s, n - 2) /
+           (fact_n1 * fact_n2);
+}
+
+void orc_cm_event(int n, double sqrt_shat, uint64_t seed, uint64_t point, double *p)
+{
+    double u[32];
+    for (int i = 0; i < n; ++i) {
+        orc_uniform_pair(seed, point, (uint32_t)(2 * i), 0, &u[4 * i]);
+        orc_uniform_pair(seed, point, (uint32_t)(2 * i + 1), 0, &u[4 * i + 2]);
+    }
+    double e = 0.5 * sqrt_shat;
+    double p1[4] = {e, 0, 0, e}, p2[4] = {e, 0, 0, -e};
+    memcpy(p, p1, sizeof p1);
+    memcpy(p + 4, p2, sizeof p2);
+    orc_rambo(n, sqrt_shat, u, p + 8);
+}
+
+void orc_cm_events(int n, double sqrt_shat, uint64_t seed, uint64_t first, int64_t np,
+                   double *p_aos)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < np; ++i)
+        orc_cm_event(n, sqrt_shat, seed, first + (uint64_t)i, p_aos + i * (n + 2) * 4);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cuts, eq. (9)-(10).  eta = rapidity (= pseudorapidity for photons).       */
+/* ------------------------------------------------------------------------ */
+int orc_pass_cuts(int n, const double *k, double y, double pt_min, double eta_max,
+                  double dr_min)
+{
+    double eta[8], phi[8];
+    for (int i = 0; i < n; ++i) {
+        const double *ki = k + 4 * i;
+        double pt = sqrt(ki[1] * ki[1] + ki[2] * ki[2]);
+        double pabs = sqrt(ki[1] * ki[1] + ki[2] * ki[2] + ki[3] * ki[3]);
+        eta[i] = atanh(ki[3] / pabs) + y;
+        phi[i] = atan2(ki[2], ki[1]);
+        if (pt_min > 0 && !(pt > pt_min)) return 0;
+        if (eta_max > 0 && !(fabs(eta[i]) < eta_max)) return 0;
+    }
+    if (dr_min > 0) {
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) {
+                double deta = eta[i] - eta[j];
+                double dphi = fabs(phi[i] - phi[j]);
+                if (dphi > M_PI) dphi = 2.0 * M_PI - dphi;
+                if (!(sqrt(deta * deta + dphi * dphi) > dr_min)) return 0;
+            }
+    }
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dirac algebra, chiral representation (the one HELAS uses):                */
+/*   gamma^0 = [[0,1],[1,0]], gamma^k = [[0,sigma^k],[-sigma^k,0]],            */
+/*   gamma5 = diag(-1,-1,1,1), P_L = (1-gamma5)/2 = diag(1,1,0,0).              */
+/* Spinors are stored as 4 complex components; a "flowing-out" wavefunction  */
+/* <fo| is a row vector (already barred).                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    cplx m[4][4];
+} mat4;
+
+static mat4 GAMMA[4];
+static int gamma_ready = 0;
+
+/* built once when the library loads, so OpenMP threads only ever read it */
+__attribute__((constructor)) static void init_gamma(void)
+{
+    if (gamma_ready) return;
+    const cplx iu = _Complex_I;
+    /* Pauli matrices */
+    cplx sig[4][2][2] = {
+        {{1, 0}, {0, 1}},
+        {{0, 1}, {1, 0}},
+        {{0, -iu}, {iu, 0}},
+        {{1, 0}, {0, -1}},
+    };
+    memset(GAMMA, 0, sizeof GAMMA);
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            GAMMA[0].m[a][2 + b] = sig[0][a][b];
+            GAMMA[0].m[2 + a][b] = sig[0][a][b];
+            for (int k = 1; k < 4; ++k) {
+                GAMMA[k].m[a][2 + b] = sig[k][a][b];
+                GAMMA[k].m[2 + a][b] = -sig[k][a][b];
+            }
+        }
+    gamma_ready = 1;
+}
+
+/* slash(a) = gamma^mu a_mu = gamma^0 a^0 - gamma^k a^k, a given with upper index */
+static mat4 slash_c(const cplx a[4])
+{
+    mat4 r;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+            r.m[i][j] = GAMMA[0].m[i][j] * a[0] - GAMMA[1].m[i][j] * a[1] -
+                        GAMMA[2].m[i][j] * a[2] - GAMMA[3].m[i][j] * a[3];
+    return r;
+}
+
+static mat4 slash_r(const double a[4])
+{
+    cplx c[4] = {a[0], a[1], a[2], a[3]};
+    return slash_c(c);
+}
+
+/* chiral coupling Gamma = gal0 P_L + gal1 P_R of the FFV Lagrangian (Appendix B.3) */
+static mat4 chiral_coupling(double gal0, double gal1)
+{
+    mat4 r;
+    memset(&r, 0, sizeof r);
+    r.m[0][0] = r.m[1][1] = gal0;
+    r.m[2][2] = r.m[3][3] = gal1;
+    return r;
+}
+
+static void row_times(const cplx v[4], const mat4 *m, cplx out[4])
+{
+    for (int j = 0; j < 4; ++j) {
+        cplx s = 0;
+        for (int i = 0; i < 4; ++i) s += v[i] * m->m[i][j];
+        out[j] = s;
+    }
+}
+
+static void mat_times(const mat4 *m, const cplx v[4], cplx out[4])
+{
+    for (int i = 0; i < 4; ++i) {
+        cplx s = 0;
+        for (int j = 0; j < 4; ++j) s += m->m[i][j] * v[j];
+        out[i] = s;
+    }
+}
+
+/* A wavefunction: 4 spinor (or polarisation) components and the momentum it
+ * carries along the fermion-number (or particle) flow, as in HELAS where
+ * components 4-5 hold the momentum times nSF (fermions) or nSV (vectors). */
+typedef struct {
+    cplx s[4];
+    double p[4];
+} wf;
+
+/* ---- external wavefunctions (Appendix B.1-B.2) ---- */
+
+/* Flowing-in massless u spinor u(p, h/2) (nSF = +1) for p on the z axis, in the
+ * HELAS phase convention.  Chirality: h = +1 lives in the lower (right-handed)
+ * pair, h = -1 in the upper (left-handed) pair, each of size sqrt(2E). */
+static wf u_spinor_z(const double p[4], int h, int along_minus_z)
+{
+    wf w;
+    memset(&w, 0, sizeof w);
+    double r = sqrt(2.0 * p[0]);
+    if (!along_minus_z) { /* ixxxx1 */
+        if (h == 1) w.s[2] = r;
+        else w.s[1] = r;
+    } else { /* ixxxx2 */
+        if (h == 1) w.s[3] = r;
+        else w.s[0] = -r;
+    }
+    for (int m = 0; m < 4; ++m) w.p[m] = p[m];
+    return w;
+}
+
+/* Flowing-out massless vbar spinor vbar(p, h/2) (nSF = -1) for p on the z axis,
+ * HELAS phase convention; the stored momentum is -p (fermion-number flow). */
+static wf vbar_spinor_z(const double p[4], int h, int along_plus_z)
+{
+    wf w;
+    memset(&w, 0, sizeof w);
+    double r = sqrt(2.0 * p[0]);
+    if (!along_plus_z) { /* oxxxx2 */
+        if (h == 1) w.s[2] = -r;
+        else w.s[1] = r;
+    } else { /* oxxxx1 */
+        if (h == 1) w.s[3] = -r;
+        else w.s[0] = -r;
+    }
+    for (int m = 0; m < 4; ++m) w.p[m] = -p[m];
+    return w;
+}
+
+/* Outgoing photon (nSV = +1): eps*(k, lam) = (-lam e_theta + i e_phi)/sqrt(2)
+ * with e_theta, e_phi the polar unit vectors of k; eps^0 = 0, so eps.k = 0
+ * and eps.n = 0 for n = (k^0, -k).  Singular for pT = 0. */
+static wf photon_eps(const double k[4], int lam)
+{
+    wf w;
+    double pt = sqrt(k[1] * k[1] + k[2] * k[2]);
+    double pabs = sqrt(pt * pt + k[3] * k[3]);
+    double ct = k[3] / pabs, st = pt / pabs;
+    double cf = k[1] / pt, sf = k[2] / pt;
+    double eth[3] = {ct * cf, ct * sf, -st};
+    double eph[3] = {-sf, cf, 0.0};
+    w.s[0] = 0;
+    for (int m = 0; m < 3; ++m)
+        w.s[m + 1] = (-lam * eth[m] + _Complex_I * eph[m]) / sqrt(2.0);
+    for (int m = 0; m < 4; ++m) w.p[m] = k[m];
+    return w;
+}
+
+/* ---- FFV vertex functions (Appendix B.3), from the Lagrangian ----
+ *   L = psibar_F1 gamma^mu (gal0 P_L + gal1 P_R) psi_F2 V*_mu,
+ * fermion propagator numerator slash(q) with factor d = -1/q^2 (massless). */
+
+static double mdot(const double a[4], const double b[4])
+{
+    return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+
+/* amplitude <fo| eps-slash Gamma |fi> (iovxx0) */
+static cplx iov(const wf *fi, const wf *fo, const wf *vc, double gal0, double gal1)
+{
+    mat4 e = slash_c(vc->s), G = chiral_coupling(gal0, gal1);
+    cplx t1[4], t2[4];
+    row_times(fo->s, &e, t1);
+    row_times(t1, &G, t2);
+    cplx r = 0;
+    for (int i = 0; i < 4; ++i) r += t2[i] * fi->s[i];
+    return r;
+}
+
+/* off-shell outgoing fermion <fo| eps-slash Gamma slash(q) (-1/q^2), q = p_fo + k (fvoxx0) */
+static wf fvo(const wf *fo, const wf *vc, double gal0, double gal1)
+{
+    wf r;
+    for (int m = 0; m < 4; ++m) r.p[m] = fo->p[m] + vc->p[m];
+    double d = -1.0 / mdot(r.p, r.p);
+    mat4 e = slash_c(vc->s), G = chiral_coupling(gal0, gal1), q = slash_r(r.p);
+    cplx t1[4], t2[4];
+    row_times(fo->s, &e, t1);
+    row_times(t1, &G, t2);
+    row_times(t2, &q, r.s);
+    for (int i = 0; i < 4; ++i) r.s[i] *= d;
+    return r;
+}
+
+/* off-shell incoming fermion (-1/q^2) slash(q) eps-slash Gamma |fi>, q = p_fi - k (fvixx0) */
+static wf fvi(const wf *fi, const wf *vc, double gal0, double gal1)
+{
+    wf r;
+    for (int m = 0; m < 4; ++m) r.p[m] = fi->p[m] - vc->p[m];
+    double d = -1.0 / mdot(r.p, r.p);
+    mat4 e = slash_c(vc->s), G = chiral_coupling(gal0, gal1), q = slash_r(r.p);
+    cplx t1[4], t2[4];
+    mat_times(&G, fi->s, t1);
+    mat_times(&e, t1, t2);
+    mat_times(&q, t2, r.s);
+    for (int i = 0; i < 4; ++i) r.s[i] *= d;
+    return r;
+}
+
+/* next permutation in lexicographic order; returns 0 after the last one */
+static int next_perm(int *a, int n)
+{
+    int i = n - 2;
+    while (i >= 0 && a[i] >= a[i + 1]) --i;
+    if (i < 0) return 0;
+    int j = n - 1;
+    while (a[j] <= a[i]) --j;
+    int t = a[i];
+    a[i] = a[j];
+    a[j] = t;
+    for (int l = i + 1, r = n - 1; l < r; ++l, --r) {
+        t = a[l];
+        a[l] = a[r];
+        a[r] = t;
+    }
+    return 1;
+}
+
+static void external_wfs(int n, const double *p, int h1, int h2, const int *lam,
+                         int u_minus_z, wf *u, wf *vb, wf *eps)
+{
+    *u = u_spinor_z(p, h1, u_minus_z);
+    *vb = vbar_spinor_z(p + 4, h2, u_minus_z);
+    for (int i = 0; i < n; ++i) eps[i] = photon_eps(p + 8 + 4 * i, lam[i]);
+}
+
+/* sum over all orderings of: ubar end -> fvo ... fvo -> iov with u (Appendix A.2) */
+static cplx ordering_sum(int n, const wf *u, const wf *vb, const wf *eps, double g,
+                         double *sum_abs)
+{
+    int a[8];
+    for (int i = 0; i < n; ++i) a[i] = i;
+    cplx total = 0;
+    double sabs = 0;
+    do {
+        wf w = *vb;
+        for (int j = 0; j < n - 1; ++j) w = fvo(&w, &eps[a[j]], g, g);
+        cplx amp = iov(u, &w, &eps[a[n - 1]], g, g);
+        total += amp;
+        sabs += cabs(amp);
+    } while (next_perm(a, n));
+    if (sum_abs) *sum_abs = sabs;
+    return total;
+}
+
+void orc_amp(int n, const double *p, int h1, int h2, const int *lam, double g,
+             int u_along_minus_z, double *re, double *im)
+{
+    init_gamma();
+    wf u, vb, eps[8];
+    external_wfs(n, p, h1, h2, lam, u_along_minus_z, &u, &vb, eps);
+    cplx r = ordering_sum(n, &u, &vb, eps, g, NULL);
+    *re = creal(r);
+    *im = cimag(r);
+}
+
+void orc_amp_from_u(int n, const double *p, int h1, int h2, const int *lam, double g,
+                    double *re, double *im)
+{
+    init_gamma();
+    wf u, vb, eps[8];
+    external_wfs(n, p, h1, h2, lam, 0, &u, &vb, eps);
+    int a[8];
+    for (int i = 0; i < n; ++i) a[i] = i;
+    cplx total = 0;
+    do {
+        wf w = u;
+        for (int j = 0; j < n - 1; ++j) w = fvi(&w, &eps[a[j]], g, g);
+        total += iov(&w, &vb, &eps[a[n - 1]], g, g);
+    } while (next_perm(a, n));
+    *re = creal(total);
+    *im = cimag(total);
+}
+
+void orc_amp_custom_eps(int n, const double *p, int h1, int h2, const double *epsv,
+                        double g, double *re, double *im, double *sum_abs)
+{
+    init_gamma();
+    wf u, vb, eps[8];
+    int lam[8] = {1, 1, 1, 1, 1, 1, 1, 1};
+    external_wfs(n, p, h1, h2, lam, 0, &u, &vb, eps);
+    for (int i = 0; i < n; ++i)
+        for (int m = 0; m < 4; ++m)
+            eps[i].s[m] = epsv[(i * 4 + m) * 2] + _Complex_I * epsv[(i * 4 + m) * 2 + 1];
+    cplx r = ordering_sum(n, &u, &vb, eps, g, sum_abs);
+    *re = creal(r);
+    *im = cimag(r);
+}
+
+/* Two-sided schedule (the current reuse of the MadGraph-generated program of
+ * Appendix A.1): every ordering a[0..n-1] (listed from the ubar end) is
+ * evaluated by meeting an outgoing current built from the ubar end over
+ * a[0..s-1] with an incoming current built from the u end over
+ * a[n-1], ..., a[s+1] at the vertex of photon a[s].  split >= 0 fixes s;
+ * split < 0 takes s = (ordering index) mod n, so every split is exercised. */
+void orc_amp_meet(int n, const double *p, int h1, int h2, const int *lam, double g,
+                  int split, double *re, double *im)
+{
+    init_gamma();
+    wf u, vb, eps[8];
+    external_wfs(n, p, h1, h2, lam, 0, &u, &vb, eps);
+    int a[8];
+    for (int i = 0; i < n; ++i) a[i] = i;
+    cplx total = 0;
+    int idx = 0;
+    do {
+        int s = split >= 0 ? split % n : idx % n;
+        wf wo = vb, wi = u;
+        for (int j = 0; j < s; ++j) wo = fvo(&wo, &eps[a[j]], g, g);
+        for (int j = n - 1; j > s; --j) wi = fvi(&wi, &eps[a[j]], g, g);
+        total += iov(&wi, &wo, &eps[a[s]], g, g);
+        ++idx;
+    } while (next_perm(a, n));
+    *re = creal(total);
+    *im = cimag(total);
+}
+
+double orc_me2(int n, const double *p, double alpha, double charge, int skip_zero,
+               int u_along_minus_z)
+{
+    init_gamma();
+    double g = -sqrt(4.0 * M_PI * alpha) * charge;
+    double sum = 0.0;
+    int lam[8];
+    for (int h1 = -1; h1 <= 1; h1 += 2)
+        for (int h2 = -1; h2 <= 1; h2 += 2) {
+            if (skip_zero && h1 == h2) continue;
+            for (int bits = 0; bits < (1 << n); ++bits) {
+                for (int i = 0; i < n; ++i) lam[i] = ((bits >> i) & 1) ? 1 : -1;
+                double re, im;
+                orc_amp(n, p, h1, h2, lam, g, u_along_minus_z, &re, &im);
+                sum += re * re + im * im;
+            }
+        }
+    return sum;
+}
+
+int orc_me2_batch(int n, int64_t np, const double *p_aos, double alpha, double charge,
+                  double *out)
+{
+    init_gamma();
+    int threads = 1;
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+#pragma omp single
+        threads = omp_get_num_threads();
+#endif
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < np; ++i)
+            out[i] = orc_me2(n, p_aos + i * (n + 2) * 4, alpha, charge, 1, 0);
+    }
+    return threads;
+}
+
+/* Subset recursion: J(S) = sum_{j in S} fvo(J(S \ j), eps_j); every J(S) carries
+ * the momentum -p2 + sum_{i in S} k_i, so the sum of currents is well defined. */
+double orc_me2_subsets(int n, const double *p, double alpha, double charge)
+{
+    init_gamma();
+    double g = -sqrt(4.0 * M_PI * alpha) * charge;
+    int full = (1 << n) - 1;
+    wf *J = (wf *)malloc(sizeof(wf) * (size_t)(1 << n));
+    double sum = 0.0;
+    int lam[8];
+    for (int h1 = -1; h1 <= 1; h1 += 2)
+        for (int h2 = -1; h2 <= 1; h2 += 2) {
+            if (h1 == h2) continue;
+            for (int bits = 0; bits < (1 << n); ++bits) {
+                for (int i = 0; i < n; ++i) lam[i] = ((bits >> i) & 1) ? 1 : -1;
+                wf u, vb, eps[8];
+                external_wfs(n, p, h1, h2, lam, 0, &u, &vb, eps);
+                J[0] = vb;
+                for (int S = 1; S < full; ++S) {
+                    wf acc;
+                    memset(&acc, 0, sizeof acc);
+                    for (int j = 0; j < n; ++j) {
+                        if (!((S >> j) & 1)) continue;
+                        wf t = fvo(&J[S & ~(1 << j)], &eps[j], g, g);
+                        for (int c = 0; c < 4; ++c) acc.s[c] += t.s[c];
+                        memcpy(acc.p, t.p, sizeof acc.p);
+                    }
+                    J[S] = acc;
+                }
+                cplx amp = 0;
+                for (int j = 0; j < n; ++j) amp += iov(&u, &J[full & ~(1 << j)], &eps[j], g, g);
+                sum += creal(amp) * creal(amp) + cimag(amp) * cimag(amp);
+            }
+        }
+    free(J);
+    return sum;
+}
+
+int orc_me2_subsets_batch(int n, int64_t np, const double *p_aos, double alpha,
+                          double charge, double *out)
+{
+    init_gamma();
+    int threads = 1;
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+#pragma omp single
+        threads = omp_get_num_threads();
+#endif
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < np; ++i)
+            out[i] = orc_me2_subsets(n, p_aos + i * (n + 2) * 4, alpha, charge);
+    }
+    return threads;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cross section, eq. (1)-(2).                                               */
+/* ------------------------------------------------------------------------ */
+double orc_gev2_fb(void) { return 0.3893793721e12; }
+
+/* eq. (2) without |M|^2: 1/(2 shat) * 1/2^2 * 1/3^2 * 3 * 1/n! * Phi_n volume * (hbar c)^2 */
+static double partonic_factor(int n, double shat)
+{
+    double nfact = 1.0;
+    for (int i = 2; i <= n; ++i) nfact *= i;
+    return 1.0 / (2.0 * shat) * 0.25 * (1.0 / 9.0) * 3.0 / nfact *
+           orc_rambo_weight(n, shat) * orc_gev2_fb();
+}
+
+int orc_point(int n, const orc_config *cfg, uint64_t point, double *p, double *y,
+              double *me2, double *w)
+{
+    double sqrt_shat = cfg->sqrt_s;
+    double fpdf = 1.0, xu = 0, xub = 0;
+    *y = 0.0;
+    *me2 = 0.0;
+    *w = 0.0;
+    if (cfg->mode == ORC_UNIFORM_SQRTSHAT) {
+        double r[2];
+        orc_uniform_pair(cfg->seed, point, 1, 1, r);
+        sqrt_shat = cfg->sqrt_shat_lo + (cfg->sqrt_shat_hi - cfg->sqrt_shat_lo) * r[0];
+    } else if (cfg->mode == ORC_PP_TOY) {
+        /* toy densities D_u = x^-0.5 (1-x)^3, D_ubar = x^-0.3 (1-x)^6, sampled
+         * as x = r^(1/a) (density a x^(a-1)) with weight D/density */
+        double r[2];
+        orc_uniform_pair(cfg->seed, point, 0, 1, r);
+        xu = pow(r[0], 1.0 / 0.5);
+        xub = pow(r[1], 1.0 / 0.7);
+        fpdf = pow(1.0 - xu, 3) / 0.5 * pow(1.0 - xub, 6) / 0.7;
+        double shat = xu * xub * cfg->sqrt_s * cfg->sqrt_s;
+        sqrt_shat = sqrt(shat);
+        if (!(sqrt_shat >= cfg->sqrt_shat_lo)) {
+            orc_cm_event(n, sqrt_shat > 0 ? sqrt_shat : 1.0, cfg->seed, point, p);
+            return 0;
+        }
+    }
+    orc_cm_event(n, sqrt_shat, cfg->seed, point, p);
+    double shat = sqrt_shat * sqrt_shat;
+    double base = partonic_factor(n, shat);
+    if (cfg->mode != ORC_PP_TOY) {
+        if (!orc_pass_cuts(n, p + 8, 0.0, cfg->pt_min, cfg->eta_max, cfg->dr_min)) return 0;
+        *me2 = orc_me2(n, p, cfg->alpha, cfg->charge, 1, 0);
+        *w = base * *me2;
+        return 1;
+    }
+    /* eq. (1): both assignments of u and ubar to the two beams.
+     * A: u from beam 1 (moves along +z), x1 = xu, x2 = xub.
+     * B: ubar from beam 1, u from beam 2; the CM event is the RAMBO event
+     *    rotated by pi about the x axis, so u moves along -z. */
+    double yA = 0.5 * log(xu / xub);
+    double yB = 0.5 * log(xub / xu);
+    *y = yA;
+    double pB[4 * 10];
+    for (int i = 0; i < n + 2; ++i) {
+        pB[4 * i + 0] = p[4 * i + 0];
+        pB[4 * i + 1] = p[4 * i + 1];
+        pB[4 * i + 2] = -p[4 * i + 2];
+        pB[4 * i + 3] = -p[4 * i + 3];
+    }
+    int passA = orc_pass_cuts(n, p + 8, yA, cfg->pt_min, cfg->eta_max, cfg->dr_min);
+    int passB = orc_pass_cuts(n, pB + 8, yB, cfg->pt_min, cfg->eta_max, cfg->dr_min);
+    double meA = passA ? orc_me2(n, p, cfg->alpha, cfg->charge, 1, 0) : 0.0;
+    double meB = passB ? orc_me2(n, pB, cfg->alpha, cfg->charge, 1, 1) : 0.0;
+    *me2 = passA ? meA : meB;
+    *w = fpdf * base * (meA + meB);
+    return passA || passB;
+}
+
+int orc_xsec(int n, const orc_config *cfg, orc_result *out, double *w_out)
+{
+    init_gamma();
+    int64_t N = cfg->npoints;
+    double *w = w_out ? w_out : (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    char *acc = (char *)malloc((size_t)(N > 0 ? N : 1));
+    int threads = 1;
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+#pragma omp single
+        threads = omp_get_num_threads();
+#endif
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < N; ++i) {
+            double p[40], y, me2;
+            acc[i] = (char)orc_point(n, cfg, (uint64_t)(cfg->first_point + i), p, &y, &me2,
+                                     &w[i]);
+        }
+    }
+    /* Neumaier summation in point order */
+    double s = 0, c = 0, s2 = 0;
+    int64_t nacc = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        double t = s + w[i];
+        if (fabs(s) >= fabs(w[i])) c += (s - t) + w[i];
+        else c += (w[i] - t) + s;
+        s = t;
+        s2 += w[i] * w[i];
+        nacc += acc[i];
+    }
+    out->sum_w = s + c;
+    out->sum_w_comp = c;
+    out->sum_w2 = s2;
+    out->n_gen = N;
+    out->n_acc = nacc;
+    double sigma = N > 0 ? (s + c) / (double)N : 0.0;
+    out->sigma_fb = sigma;
+    out->err_fb = N > 1 ? sqrt(fmax(s2 / (double)N - sigma * sigma, 0.0) / (double)(N - 1)) : 0.0;
+    free(acc);
+    if (!w_out) free(w);
+    return threads;
+}
