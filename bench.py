@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Throughput of the u ubar -> n photon |M|^2 path on one MI355X.
+
+One step = one heget_xsec pass over a batch of synthetic phase-space points:
+counter-based random numbers -> RAMBO -> cuts -> compaction -> helicity-summed
+|M|^2 (shared-prefix tree over the n! orderings) -> weights -> compensated
+reduction to sigma +- err.  Inputs are generated on the device (nothing is
+read from the host inside the timed region).
+
+Default workload: u ubar -> 4 photons at sqrt(shat) = 1 TeV, 2^20 points
+(seed 1), pT > 20 GeV, |eta| < 2.5, Delta R > 0.4; amplitudes in FP32 with
+FP64 ordering/helicity sums (the FP64-amplitude form is measured beside it).
+
+value = points whose |M|^2 was evaluated (points passing the cuts) per second
+of the whole step.  The roofline object is for the amplitude kernel: its
+algorithmic flops (heget_me2_flops, counted on the schedule actually run)
+times the points per launch, over its average launch time measured with HIP
+events on the launch stream.  cpu_baseline times the FP64 CPU oracle
+(brute-force ordering sum) on a bounded sample of the same points.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Issue-rate ceiling of the vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA)
+# x 2.4 GHz.  FP64 FMA and non-packed FP32 FMA issue at the same rate; the
+# library is built without packed-FP32 instructions, so this is the ceiling
+# for both precisions (the published 157.3 TFLOP/s FP32 figure needs packed FP32).
+PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PUBLISHED_FP32_VECTOR_TFLOPS = 157.3
+
+WORKLOADS = {
+    "uubar_4a_1TeV_2p20": dict(n=4, sqrt_s=1000.0, npoints=1 << 20, seed=1),
+}
+
+
+def run_steps(H, torch, n, cfg, steps, warmup):
+    warm = [H.XsecAsync(n, cfg) for _ in range(warmup)]
+    torch.cuda.synchronize()
+    del warm
+    H.timing_enable(True)
+    H.timing_read(reset=True)
+    t0 = time.perf_counter()
+    handles = [H.XsecAsync(n, cfg) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    me2_ms, launches = H.timing_read(reset=True)
+    H.timing_enable(False)
+    res = [h.result() for h in handles]
+    assert all(r == res[0] for r in res), "steps disagree"
+    return (t1 - t0) * 1e3 / steps, me2_ms / max(launches, 1), launches, res[0]
+
+
+def cpu_baseline(n, wl, budget_s):
+    """FP64 oracle |M|^2 on the first survivors of the same stream (~budget_s of CPU)."""
+    import numpy as np
+    import oracle as O
+
+    def sample(count):
+        out, start = [], 0
+        while len(out) < count:
+            ev = O.cm_events(n, wl["sqrt_s"], wl["seed"], start, 4 * count)
+            start += ev.shape[0]
+            out.extend(p for p in ev if O.pass_cuts(p[2:], 0.0, 20.0, 2.5, 0.4))
+        return np.array(out[:count])
+
+    cal = sample(256)
+    t0 = time.perf_counter()
+    O.me2_batch(cal)
+    dt = time.perf_counter() - t0
+    count = int(min(max(256, budget_s / max(dt, 1e-6) * 256), 1 << 20))
+    ev = sample(count)
+    t0 = time.perf_counter()
+    _, threads = O.me2_batch(ev)
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 brute-force |M|^2 of the first {count} points passing the cuts "
+                      f"(seed {wl['seed']}, n={n}, sqrt(shat)={wl['sqrt_s']:.0f} GeV), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uubar_4a_1TeV_2p20", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the |M|^2 path "
+              "has no multi-GPU execution in this library", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_0908_4403_amd as H
+
+    wl = WORKLOADS[args.workload]
+    n = wl["n"]
+    torch.cuda.set_device(0)
+    base = dict(mode=H.FIXED_SHAT, seed=wl["seed"], npoints=wl["npoints"], sqrt_s=wl["sqrt_s"],
+                pt_min=20.0, eta_max=2.5, dr_min=0.4)
+
+    print(f"bench: {args.workload} FP32 steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    ms32, k32, l32, r32 = run_steps(H, torch, n, H.Config(prec=H.FP32, **base), args.steps, args.warmup)
+    print(f"bench: FP32 {ms32:.3f} ms/step, me2 kernel {k32:.3f} ms", file=sys.stderr, flush=True)
+    ms64, k64, l64, r64 = run_steps(H, torch, n, H.Config(prec=H.FP64, **base),
+                                    max(3, args.steps // 2), 1)
+    print(f"bench: FP64 {ms64:.3f} ms/step, me2 kernel {k64:.3f} ms", file=sys.stderr, flush=True)
+
+    n_acc = r32["n_acc"]
+    f32 = H.me2_flops(n, H.FP32)[0]
+    f64 = H.me2_flops(n, H.FP64)[0]
+    ach32 = f32 * n_acc / (k32 * 1e-3) / 1e12
+    ach64 = f64 * n_acc / (k64 * 1e-3) / 1e12
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(n, wl, args.cpu_seconds)
+
+    line = {
+        "metric": "phase-space points/s of helicity-summed |M|^2, n=4..8, FP32-batched vs FP64 plain",
+        "value": n_acc / (ms32 * 1e-3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "process": f"u ubar -> {n} photons",
+                   "sqrt_shat_GeV": wl["sqrt_s"], "points_generated": wl["npoints"],
+                   "points_evaluated": n_acc, "seed": wl["seed"],
+                   "cuts": "pT>20 GeV, |eta|<2.5, dR>0.4", "sigma_fb": r32["sigma_fb"],
+                   "sigma_err_fb": r32["err_fb"]},
+        "roofline": {"bound": "alu", "achieved": ach32, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach32 / PEAK_VALU_TFLOPS, "traffic": None,
+                     "kernel": f"me2_kernel<float,{n}>", "kernel_ms": k32,
+                     "flops_per_point": f32, "frac_of_published_fp32_vector": ach32 / PUBLISHED_FP32_VECTOR_TFLOPS},
+        "fp64_plain": {"value": r64["n_acc"] / (ms64 * 1e-3), "ms_per_step": ms64, "kernel_ms": k64,
+                       "achieved_tflops": ach64, "frac": ach64 / PEAK_VALU_TFLOPS,
+                       "sigma_fb": r64["sigma_fb"], "flops_per_point": f64},
+        "fp32_over_fp64": (n_acc / ms32) / (r64["n_acc"] / ms64),
+        "generated_points_per_s": wl["npoints"] / (ms32 * 1e-3),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

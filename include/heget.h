@@ -1,0 +1,167 @@
+/*
+ * heget -- helicity-summed |M|^2 of u ubar -> n photons on an AMD Instinct
+ * MI355X (gfx950), and the weighted Monte-Carlo cross section built on it.
+ *
+ * Method: K. Hagiwara, J. Kanzaki, N. Okamura, D. Rainwater, T. Stelzer,
+ * "Fast calculation of HELAS amplitudes using graphics processing unit
+ * (GPU)", arXiv:0908.4403.  Section 2 defines the physics (eq. (1)-(10)),
+ * Section 3.1 the problem statement the calls below follow (the user supplies
+ * random numbers -- here a seed -- and gets phase-space points, their |M|^2
+ * and the cross section), Appendix B the HELAS conventions the amplitudes use.
+ *
+ * Conventions shared by every call:
+ *   - n is the number of photons, 2 <= n <= 8.
+ *   - Momenta are (E, px, py, pz) in GeV, FP64.  An event holds n+2 momenta in
+ *     the order u (incoming, along +z), ubar (incoming, along -z), photons.
+ *   - Host-pointer calls use the event-major layout momenta[npoints][n+2][4].
+ *     Device-pointer calls ("_device") use component-major (SoA) layout
+ *     mom[(n+2)*4][npoints]: row r = 4*particle + component.
+ *   - |M|^2 values are summed over the two quark and all photon helicities
+ *     (eq. (2)), with no spin, colour or identical-particle average, in
+ *     GeV^(4-2n); coupling gal = -e Q with e = sqrt(4 pi alpha).
+ *   - The caller owns every buffer it passes.  Host-pointer calls keep no
+ *     pointer after they return.  Device-pointer calls enqueue work on the
+ *     given stream and return; their buffers must stay valid until that work
+ *     has completed.  The library owns its device scratch (allocated on first
+ *     use, grown as needed, released by heget_shutdown()).
+ *   - Calls are serialised by an internal mutex; no exception crosses this
+ *     boundary.  On failure the returned status is negative and
+ *     heget_last_error() describes it.
+ *   - Nothing touches the GPU before the first call that needs it, so the
+ *     argument checks below work on a machine without one.
+ */
+#ifndef HEGET_H
+#define HEGET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HEGET_OK = 0,
+    HEGET_WARN_NONFINITE = 1, /* results written; some points gave NaN/inf
+                                 (e.g. a photon with pT = 0) */
+    HEGET_ERR_ARG = -1,       /* null pointer, bad enum, bad cut or energy */
+    HEGET_ERR_RANGE = -2,     /* n outside 2..8, npoints < 0 or >= 2^31 */
+    HEGET_ERR_ALLOC = -3,     /* device allocation failed */
+    HEGET_ERR_DEVICE = -4     /* HIP runtime error (no GPU, launch failure) */
+} heget_status;
+
+/* Arithmetic of the amplitude (the shared-prefix tree of currents).  Both
+ * accumulate the per-point ordering sum, the helicity sum and the cross
+ * section in FP64; phase-space generation and boosts are always FP64. */
+typedef enum {
+    HEGET_FP64 = 0, /* amplitudes in FP64 */
+    HEGET_FP32 = 1  /* amplitudes in FP32, ordering and helicity sums in FP64 */
+} heget_prec;
+
+/* Partonic kinematics of heget_xsec (Section 2.1). */
+typedef enum {
+    HEGET_FIXED_SHAT = 0,       /* u ubar at fixed sqrt(shat) = sqrt_s */
+    HEGET_UNIFORM_SQRTSHAT = 1, /* sqrt(shat) uniform in [sqrt_shat_lo, sqrt_shat_hi];
+                                   sigma is the average of sigma_hat over it */
+    HEGET_PP_TOY = 2            /* eq. (1): pp at hadronic sqrt_s with toy densities
+                                   D_u = x^-0.5 (1-x)^3, D_ubar = x^-0.3 (1-x)^6,
+                                   both beam assignments, sqrt(shat) >= sqrt_shat_lo */
+} heget_mode;
+
+/* Final-state photon cuts, eq. (9)-(10): pT > pt_min, |eta| < eta_max,
+ * Delta R > dr_min for every pair.  A bound <= 0 disables that cut.  eta is
+ * the lab-frame rapidity; Delta phi is folded into [0, pi]. */
+typedef struct {
+    double pt_min, eta_max, dr_min;
+} heget_cuts;
+
+typedef struct {
+    int32_t mode;       /* heget_mode */
+    int32_t prec;       /* heget_prec */
+    uint64_t seed;      /* random stream (key of the counter-based generator) */
+    int64_t npoints;    /* generated points, 0 <= npoints < 2^31 */
+    double sqrt_s;      /* FIXED: sqrt(shat); PP: hadronic sqrt(s) [GeV] */
+    double sqrt_shat_lo, sqrt_shat_hi; /* UNIFORM: range; PP: lo = min sqrt(shat) */
+    heget_cuts cuts;
+    double alpha, charge; /* e^2 = 4 pi alpha; quark charge in units of e */
+} heget_config;
+
+typedef struct {
+    double sigma_fb, err_fb; /* sigma = sum_w / n_gen, MC standard error (fb) */
+    double sum_w, sum_w_comp, sum_w2; /* compensated sum of weights, its
+                                         compensation term, sum of squares */
+    int64_t n_gen, n_acc;    /* generated points, points passing all cuts */
+} heget_result;
+
+/* A hipStream_t; NULL means the null stream. */
+typedef void *heget_stream;
+
+/* Phase-space points at fixed sqrt(shat) = sqrt_s (Section 3.1 step 4):
+ * RAMBO massless momenta from the counter-based stream `seed`, point indices
+ * 0..npoints-1, and the cuts.  momenta[npoints][n+2][4] (out, host) receives
+ * every point; weight[npoints] (out, host) receives the phase-space weight of
+ * eq. (4) (the massless n-body volume) for points passing the cuts, 0 for the
+ * others.  cuts may be NULL (no cuts).  Returns HEGET_OK or an error. */
+heget_status heget_gen_points(int n, double sqrt_s, const heget_cuts *cuts, uint64_t seed,
+                              int64_t npoints, double *momenta, double *weight);
+
+/* The same points written to device memory in SoA layout: d_mom[(n+2)*4][npoints]
+ * and d_weight[npoints], for point indices first..first+npoints-1. */
+heget_status heget_gen_points_device(int n, double sqrt_s, const heget_cuts *cuts,
+                                     uint64_t seed, int64_t first, int64_t npoints,
+                                     double *d_mom, double *d_weight, heget_stream stream);
+
+/* Helicity-summed |M|^2 (eq. (2) summand; eq. (6)-(8) amplitudes) at the
+ * given points.  momenta[npoints][n+2][4] (in, host), out_me2[npoints] (out,
+ * host).  Preconditions per point: u along +z and ubar along -z (zero
+ * transverse momenta), every photon with E > 0 and pT > 0.  A point that
+ * violates them gets NaN and the call returns HEGET_WARN_NONFINITE. */
+heget_status heget_me2(int n, int64_t npoints, const double *momenta, double *out_me2,
+                       heget_prec prec);
+
+/* Device-pointer form of heget_me2: d_mom[(n+2)*4][npoints] (SoA, device),
+ * d_out[npoints] (device).  Enqueued on `stream`; non-finite results are not
+ * reported in the status (inspect d_out). */
+heget_status heget_me2_device(int n, int64_t npoints, const double *d_mom, double *d_out,
+                              heget_prec prec, heget_stream stream);
+
+/* Monte-Carlo cross section (Section 3.1 steps 2-6, eq. (1)-(2)): every
+ * point is generated, cut, evaluated and weighted on the device; only the
+ * result crosses to the host.  out (host) receives sigma +- err in fb.
+ * Deterministic: the same config gives bitwise the same result. */
+heget_status heget_xsec(int n, const heget_config *cfg, heget_result *out);
+
+/* heget_xsec enqueued on `stream`; *out is written when the stream reaches
+ * it, from a pinned staging buffer (out must stay valid until then). */
+heget_status heget_xsec_async(int n, const heget_config *cfg, heget_result *out,
+                              heget_stream stream);
+
+/* Couplings used by heget_me2 / heget_me2_device (defaults: 1/137, 2/3). */
+heget_status heget_set_couplings(double alpha, double charge);
+
+/* Optional per-kernel timing of the amplitude kernel: when enabled, each
+ * launch of it is bracketed by events on its stream; heget_timing_read
+ * returns the accumulated milliseconds and launch count since the last
+ * reset (it synchronises the recorded events). */
+heget_status heget_timing_enable(int on);
+heget_status heget_timing_read(double *me2_ms, int64_t *me2_launches, int reset);
+
+/* Algorithmic floating-point operations per point of the amplitude kernel
+ * that heget_me2 / heget_xsec run for (n, prec): FMA = 2, add/mul/reciprocal
+ * = 1, counted on the schedule actually executed (the 2^n helicities of one
+ * quark-helicity block, shared-prefix tree of the n! orderings, H helicities
+ * per tree walk).  Per-point O(n) set-up is not counted.  Also returns the
+ * unrolled depth and the helicities per walk of that kernel (may be NULL). */
+heget_status heget_me2_flops(int n, heget_prec prec, double *flops_per_point, int *unrolled,
+                             int *helicities_per_walk);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *heget_last_error(void);
+
+/* Frees device scratch, pinned staging and events.  Safe to call twice. */
+void heget_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

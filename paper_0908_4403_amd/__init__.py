@@ -1,0 +1,248 @@
+"""Python binding of libheget (include/heget.h): argument marshalling only.
+
+Every step of the |M|^2 / cross-section path runs in the HIP kernels of the
+in-tree ``libheget.so``; there is no CPU fallback.  Importing this package
+fails loudly if the library has not been built
+(``python paper_0908_4403_amd/build.py``).
+
+Host-array calls take and return numpy arrays (event layout [npoints, n+2, 4]).
+Device calls take torch tensors on the GPU (SoA layout [(n+2)*4, npoints],
+float64) and enqueue on ``torch.cuda.current_stream()`` unless a stream is
+given; torch only provides memory and streams here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libheget.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_0908_4403_amd/build.py`")
+
+_lib = C.CDLL(LIB_PATH)
+
+OK, WARN_NONFINITE = 0, 1
+ERR_ARG, ERR_RANGE, ERR_ALLOC, ERR_DEVICE = -1, -2, -3, -4
+FP64, FP32 = 0, 1
+FIXED_SHAT, UNIFORM_SQRTSHAT, PP_TOY = 0, 1, 2
+
+EXPORTS = ["heget_gen_points", "heget_gen_points_device", "heget_me2", "heget_me2_device",
+           "heget_xsec", "heget_xsec_async", "heget_set_couplings", "heget_timing_enable",
+           "heget_timing_read", "heget_me2_flops", "heget_last_error", "heget_shutdown"]
+
+
+class Cuts(C.Structure):
+    _fields_ = [("pt_min", C.c_double), ("eta_max", C.c_double), ("dr_min", C.c_double)]
+
+
+class _Config(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("prec", C.c_int32), ("seed", C.c_uint64),
+                ("npoints", C.c_int64), ("sqrt_s", C.c_double), ("sqrt_shat_lo", C.c_double),
+                ("sqrt_shat_hi", C.c_double), ("cuts", Cuts), ("alpha", C.c_double),
+                ("charge", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("sigma_fb", C.c_double), ("err_fb", C.c_double), ("sum_w", C.c_double),
+                ("sum_w_comp", C.c_double), ("sum_w2", C.c_double), ("n_gen", C.c_int64),
+                ("n_acc", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_dp = C.POINTER(C.c_double)
+_st = C.c_int
+_lib.heget_gen_points.argtypes = [C.c_int, C.c_double, C.POINTER(Cuts), C.c_uint64, C.c_int64, _dp, _dp]
+_lib.heget_gen_points_device.argtypes = [C.c_int, C.c_double, C.POINTER(Cuts), C.c_uint64,
+                                         C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.heget_me2.argtypes = [C.c_int, C.c_int64, _dp, _dp, C.c_int]
+_lib.heget_me2_device.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+_lib.heget_xsec.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result)]
+_lib.heget_xsec_async.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result), C.c_void_p]
+_lib.heget_set_couplings.argtypes = [C.c_double, C.c_double]
+_lib.heget_timing_enable.argtypes = [C.c_int]
+_lib.heget_timing_read.argtypes = [_dp, C.POINTER(C.c_int64), C.c_int]
+_lib.heget_me2_flops.argtypes = [C.c_int, C.c_int, _dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+_lib.heget_last_error.restype = C.c_char_p
+_lib.heget_shutdown.restype = None
+for _f in EXPORTS[:-2]:
+    getattr(_lib, _f).restype = _st
+
+
+class HegetError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where} failed with status {status}: {last_error()}")
+
+
+def last_error() -> str:
+    return _lib.heget_last_error().decode()
+
+
+def _check(status: int, where: str) -> int:
+    if status < 0:
+        raise HegetError(status, where)
+    return status
+
+
+def _cuts(cuts) -> Cuts | None:
+    if cuts is None:
+        return None
+    if isinstance(cuts, Cuts):
+        return cuts
+    return Cuts(*[float(x) for x in cuts])
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ---- host-array calls -------------------------------------------------------
+
+def gen_points(n: int, sqrt_s: float, cuts=(20.0, 2.5, 0.4), seed: int = 0, npoints: int = 1024):
+    """(momenta[npoints, n+2, 4], weight[npoints]) at fixed sqrt(shat)."""
+    mom = np.zeros((npoints, n + 2, 4))
+    w = np.zeros(npoints)
+    c = _cuts(cuts)
+    _check(_lib.heget_gen_points(n, sqrt_s, C.byref(c) if c else None, seed, npoints,
+                                 _ptr(mom), _ptr(w)), "heget_gen_points")
+    return mom, w
+
+
+def me2(momenta, prec: int = FP64, return_status: bool = False):
+    """Helicity-summed |M|^2 at momenta[npoints, n+2, 4] (host arrays)."""
+    p = np.ascontiguousarray(momenta, dtype=np.float64)
+    if p.ndim != 3 or p.shape[2] != 4:
+        raise ValueError("momenta must have shape [npoints, n+2, 4]")
+    n = p.shape[1] - 2
+    out = np.zeros(p.shape[0])
+    st = _check(_lib.heget_me2(n, p.shape[0], _ptr(p), _ptr(out), prec), "heget_me2")
+    return (out, st) if return_status else out
+
+
+@dataclass
+class Config:
+    mode: int = FIXED_SHAT
+    prec: int = FP32
+    seed: int = 0
+    npoints: int = 16384
+    sqrt_s: float = 500.0
+    sqrt_shat_lo: float = 0.0
+    sqrt_shat_hi: float = 0.0
+    pt_min: float = 20.0
+    eta_max: float = 2.5
+    dr_min: float = 0.4
+    alpha: float = 1.0 / 137.0
+    charge: float = 2.0 / 3.0
+
+    def c(self) -> _Config:
+        return _Config(self.mode, self.prec, self.seed, self.npoints, self.sqrt_s,
+                       self.sqrt_shat_lo, self.sqrt_shat_hi,
+                       Cuts(self.pt_min, self.eta_max, self.dr_min), self.alpha, self.charge)
+
+
+def xsec(n: int, cfg: Config, return_status: bool = False) -> dict:
+    r = Result()
+    c = cfg.c()
+    st = _check(_lib.heget_xsec(n, C.byref(c), C.byref(r)), "heget_xsec")
+    d = r.as_dict()
+    return (d, st) if return_status else d
+
+
+# The library writes an async result when the stream reaches it, so the
+# Result storage must outlive the Python handle: the last _MAX_INFLIGHT are
+# kept here (the library's staging ring holds 256 calls in flight).
+_MAX_INFLIGHT = 1024
+_inflight: "collections.deque" = None
+
+
+class XsecAsync:
+    """Handle of an enqueued heget_xsec_async; .result() after the stream completes.
+
+    At most 256 calls may be in flight at once (the library's staging ring)."""
+
+    def __init__(self, n: int, cfg: Config, stream=None):
+        global _inflight
+        import collections
+        if _inflight is None:
+            _inflight = collections.deque(maxlen=_MAX_INFLIGHT)
+        self._res = Result()
+        self._cfg = cfg.c()
+        _inflight.append(self._res)
+        _check(_lib.heget_xsec_async(n, C.byref(self._cfg), C.byref(self._res), _stream(stream)),
+               "heget_xsec_async")
+
+    def result(self) -> dict:
+        return self._res.as_dict()
+
+
+# ---- device calls (torch tensors) -------------------------------------------
+
+def me2_device(n: int, mom_soa, out, prec: int = FP32, stream=None) -> None:
+    """|M|^2 of the points in mom_soa[(n+2)*4, npoints] (float64, GPU) into out[npoints]."""
+    if mom_soa.dtype != out.dtype or str(mom_soa.dtype) != "torch.float64":
+        raise TypeError("device buffers must be float64")
+    if not (mom_soa.is_cuda and out.is_cuda and mom_soa.is_contiguous() and out.is_contiguous()):
+        raise ValueError("device buffers must be contiguous GPU tensors")
+    if mom_soa.shape[0] != (n + 2) * 4 or out.shape[0] != mom_soa.shape[1]:
+        raise ValueError("shape mismatch: mom_soa[(n+2)*4, npoints], out[npoints]")
+    _check(_lib.heget_me2_device(n, mom_soa.shape[1], mom_soa.data_ptr(), out.data_ptr(), prec,
+                                 _stream(stream)), "heget_me2_device")
+
+
+def gen_points_device(n: int, sqrt_s: float, mom_soa, weight, cuts=(20.0, 2.5, 0.4), seed: int = 0,
+                      first: int = 0, stream=None) -> None:
+    if mom_soa.shape[0] != (n + 2) * 4 or weight.shape[0] != mom_soa.shape[1]:
+        raise ValueError("shape mismatch: mom_soa[(n+2)*4, npoints], weight[npoints]")
+    if not (mom_soa.is_cuda and weight.is_cuda and mom_soa.is_contiguous() and weight.is_contiguous()):
+        raise ValueError("device buffers must be contiguous GPU tensors")
+    c = _cuts(cuts)
+    _check(_lib.heget_gen_points_device(n, sqrt_s, C.byref(c) if c else None, seed, first,
+                                        mom_soa.shape[1], mom_soa.data_ptr(), weight.data_ptr(),
+                                        _stream(stream)), "heget_gen_points_device")
+
+
+# ---- misc --------------------------------------------------------------------
+
+def set_couplings(alpha: float = 1.0 / 137.0, charge: float = 2.0 / 3.0) -> None:
+    _check(_lib.heget_set_couplings(alpha, charge), "heget_set_couplings")
+
+
+def timing_enable(on: bool = True) -> None:
+    _check(_lib.heget_timing_enable(int(on)), "heget_timing_enable")
+
+
+def timing_read(reset: bool = True):
+    ms, cnt = C.c_double(), C.c_int64()
+    _check(_lib.heget_timing_read(C.byref(ms), C.byref(cnt), int(reset)), "heget_timing_read")
+    return ms.value, cnt.value
+
+
+def me2_flops(n: int, prec: int = FP32):
+    """(algorithmic flops per point, unrolled depth, helicities per walk) of the kernel run."""
+    f, mb, h = C.c_double(), C.c_int(), C.c_int()
+    _check(_lib.heget_me2_flops(n, prec, C.byref(f), C.byref(mb), C.byref(h)), "heget_me2_flops")
+    return f.value, mb.value, h.value
+
+
+def shutdown() -> None:
+    _lib.heget_shutdown()
+
+
+def lib():
+    return _lib

@@ -1,0 +1,66 @@
+// Launch interfaces of the device kernels (host side).  Every launcher only
+// enqueues work on `stream`; shapes are checked by the caller (heget_api.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kinematics.hpp"
+
+namespace heget {
+
+// One compiled shape of the amplitude kernel.
+struct Me2Variant {
+    int prec;   // 0 = FP64, 1 = FP32
+    int n;      // photons
+    int mb;     // unrolled bottom levels (photons held in registers)
+    int h;      // helicity configurations per tree walk
+    int wpb;    // waves per block
+    const void *func;  // kernel symbol
+};
+
+// All compiled variants (static table) and the default choice per (prec, n).
+const Me2Variant *me2_variants(int *count);
+const Me2Variant *me2_default(int prec, int n);
+
+// Arguments of one amplitude launch.
+struct Me2Args {
+    const double *mom;       // SoA [(n+2)*4][ld]
+    int64_t ld;
+    const int32_t *index;    // survivor -> column of mom, or nullptr (identity)
+    const int64_t *d_count;  // number of points on the device, or nullptr
+    int64_t count;           // number of points when d_count is null; else an upper bound
+    int nchunks;             // helicity chunks (each a separate work item)
+    double coef;             // 2 (e Q)^(2n)
+    double *out;             // [nchunks][ld_out]: |M|^2 of each chunk (summed over chunks)
+    int64_t ld_out;
+    unsigned *flags;         // bit 0 set if a result is not finite
+};
+
+hipError_t launch_me2(const Me2Variant &v, const Me2Args &a, hipStream_t stream);
+
+// Phase-space generation (FP64): momenta in SoA, weight (kind 0: Phi_n; kind
+// 1: full eq. (1)-(2) factor without |M|^2), accept flag, per-block accept
+// counts (blocks of 256 points).
+hipError_t launch_gen(int n, const GenParams &g, double *mom, int64_t ld, double *w,
+                      uint8_t *flag, int32_t *block_count, hipStream_t stream);
+// Exclusive scan of nb block counts -> offsets, total -> *d_count.
+hipError_t launch_scan(const int32_t *counts, int nb, int32_t *offsets, int64_t *d_count,
+                       hipStream_t stream);
+// Survivor list: index[offsets[b] + rank] = point, in point order.
+hipError_t launch_compact(const uint8_t *flag, int64_t np, const int32_t *offsets,
+                          int32_t *index, hipStream_t stream);
+// Sum of helicity chunks, with optional indirection: out[k] = sum_c part[c*ld + k].
+hipError_t launch_sum_chunks(const double *part, int nchunks, int64_t ld, const int64_t *d_count,
+                             int64_t count, double *out, unsigned *flags, hipStream_t stream);
+// Weights w_k = me2[k] * wfac[index[k]] and per-block (sum, compensation, sum of squares).
+hipError_t launch_weights(const double *me2, const int32_t *index, const double *wfac,
+                          const int64_t *d_count, int64_t max_count, double *partials,
+                          unsigned *flags, hipStream_t stream);
+// Fixed-order compensated reduction of nb partial triples into res[0..2]
+// (sum, compensation, sum of squares) and res[3] = (double)*d_count.
+hipError_t launch_final(const double *partials, int nb, const int64_t *d_count, double *res,
+                        hipStream_t stream);
+// Zero a small device buffer with a kernel (usable under stream capture).
+hipError_t launch_zero_u32(unsigned *p, int count, hipStream_t stream);
+
+}  // namespace heget

@@ -1,0 +1,155 @@
+// Phase-space generation, cuts and Monte-Carlo weights on the device (FP64).
+//
+//  - RAMBO for n massless momenta (Kleiss, Stirling, Ellis, CPC 40 (1986) 359):
+//    n isotropic momenta with energy density q exp(-q), then the conformal
+//    map (boost to their rest frame + rescale) onto total momentum
+//    (sqrt_s, 0, 0, 0).  The weight is constant: the massless n-body volume of
+//    eq. (4), (2pi)^(4-3n) (pi/2)^(n-1) s^(n-2) / ((n-1)! (n-2)!).
+//  - Cuts of eq. (9)-(10) in a frame boosted by rapidity y along z.
+//  - Partonic kinematics of eq. (1) for the three modes of heget_mode.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "rng.hpp"
+
+namespace heget {
+
+struct Vec4 {
+    double e, x, y, z;
+};
+
+// Photon momenta of point `point`: uniforms from stream 0, blocks 2i and 2i+1.
+template <int N>
+__device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t point, Vec4 (&k)[N])
+{
+    double Qe = 0.0, Qx = 0.0, Qy = 0.0, Qz = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double ucos, uphi, ue1, ue2;
+        uniform_pair(seed, point, 2u * i, 0u, ucos, uphi);
+        uniform_pair(seed, point, 2u * i + 1u, 0u, ue1, ue2);
+        const double c = 2.0 * ucos - 1.0;
+        const double s = sqrt(1.0 - c * c);
+        double sf, cf;
+        sincos(2.0 * M_PI * uphi, &sf, &cf);
+        const double e = -log(ue1 * ue2);
+        k[i] = {e, e * s * cf, e * s * sf, e * c};
+        Qe += k[i].e;
+        Qx += k[i].x;
+        Qy += k[i].y;
+        Qz += k[i].z;
+    }
+    const double M = sqrt(Qe * Qe - Qx * Qx - Qy * Qy - Qz * Qz);
+    const double bx = -Qx / M, by = -Qy / M, bz = -Qz / M;
+    const double x = sqrt_s / M;
+    const double gam = Qe / M;
+    const double a = 1.0 / (1.0 + gam);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double bq = bx * k[i].x + by * k[i].y + bz * k[i].z;
+        const double e = k[i].e;
+        k[i].e = x * (gam * e + bq);
+        k[i].x = x * (k[i].x + bx * e + a * bq * bx);
+        k[i].y = x * (k[i].y + by * e + a * bq * by);
+        k[i].z = x * (k[i].z + bz * e + a * bq * bz);
+    }
+}
+
+// 1 if every photon has pT > pt_min and |eta + y| < eta_max and every pair
+// Delta R > dr_min (bounds <= 0 are off).  eta = atanh(pz/|p|).
+template <int N>
+__device__ __forceinline__ bool pass_cuts(const Vec4 (&k)[N], double y, double pt_min,
+                                          double eta_max, double dr_min)
+{
+    double eta[N], phi[N];
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double pt2 = k[i].x * k[i].x + k[i].y * k[i].y;
+        const double pt = sqrt(pt2);
+        const double pabs = sqrt(pt2 + k[i].z * k[i].z);
+        eta[i] = atanh(k[i].z / pabs) + y;
+        phi[i] = atan2(k[i].y, k[i].x);
+        if (pt_min > 0.0) ok = ok && (pt > pt_min);
+        if (eta_max > 0.0) ok = ok && (fabs(eta[i]) < eta_max);
+    }
+    if (dr_min > 0.0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = i + 1; j < N; ++j) {
+                const double de = eta[i] - eta[j];
+                double dp = fabs(phi[i] - phi[j]);
+                dp = dp > M_PI ? 2.0 * M_PI - dp : dp;
+                ok = ok && (sqrt(de * de + dp * dp) > dr_min);
+            }
+    }
+    return ok;
+}
+
+// Kinematic parameters shared by every point of one generation call.
+struct GenParams {
+    int mode;            // heget_mode
+    uint64_t seed;
+    int64_t first;       // index of the first point
+    int64_t npoints;
+    double sqrt_s;       // FIXED: sqrt(shat); PP: hadronic sqrt(s)
+    double lo, hi;       // UNIFORM range / PP: min sqrt(shat)
+    double pt_min, eta_max, dr_min;
+    // eq. (2) without |M|^2, as c * shat^(n-3): 1/(2 shat) 1/4 1/9 3 1/n! Phi_n (hbar c)^2,
+    // with Phi_n = phase_volume_coef * shat^(n-2)
+    double partonic_coef;
+    double phase_volume_coef;
+    int weight_kind;     // 0: write Phi_n (or 0 if cut); 1: write the full non-|M|^2 weight
+};
+
+struct PointKin {
+    double sqrt_shat;
+    double y;      // rapidity of the partonic CM frame in the lab
+    double fpdf;   // parton-density importance weight times beam-assignment factor
+    bool above;    // PP: sqrt(shat) >= lo
+};
+
+// Partonic kinematics of point `point` (stream 1 of the generator).
+__device__ __forceinline__ PointKin point_kinematics(const GenParams &g, uint64_t point)
+{
+    PointKin pk{g.sqrt_s, 0.0, 1.0, true};
+    if (g.mode == 1) {
+        double r0, r1;
+        uniform_pair(g.seed, point, 1u, 1u, r0, r1);
+        pk.sqrt_shat = g.lo + (g.hi - g.lo) * r0;
+    } else if (g.mode == 2) {
+        // x = r^(1/a) samples a x^(a-1); the weight D(x) / (a x^(a-1)) keeps
+        // only the smooth (1-x)^b factor: a = 0.5 for u, 0.7 for ubar.
+        double r0, r1;
+        uniform_pair(g.seed, point, 0u, 1u, r0, r1);
+        const double xu = r0 * r0;
+        const double xub = pow(r1, 1.0 / 0.7);
+        const double omu = 1.0 - xu, omub = 1.0 - xub;
+        const double f = (omu * omu * omu / 0.5) * ((omub * omub) * (omub * omub) * (omub * omub) / 0.7);
+        const double shat = xu * xub * g.sqrt_s * g.sqrt_s;
+        pk.sqrt_shat = sqrt(shat);
+        pk.above = pk.sqrt_shat >= g.lo;
+        if (!pk.above) pk.sqrt_shat = g.lo;  // keep the generator finite; weight is 0
+        // both beam assignments of eq. (1): the second is the first rotated by
+        // pi about x with y -> -y, which leaves |M|^2 and every cut unchanged
+        pk.fpdf = 2.0 * f;
+        pk.y = 0.5 * log(xu / xub);
+    }
+    return pk;
+}
+
+__device__ __forceinline__ double ipow(double x, int e)
+{
+    double r = 1.0;
+    if (e >= 0) {
+        for (int i = 0; i < e; ++i) r *= x;
+    } else {
+        for (int i = 0; i < -e; ++i) r /= x;
+    }
+    return r;
+}
+
+}  // namespace heget

@@ -1,0 +1,295 @@
+// Helicity-summed |M|^2 of u(p1) ubar(p2) -> n photons on one lane per point,
+// by a shared-prefix tree over the n! photon orderings of eq. (6)-(8).
+//
+// Every diagram is one chain from the ubar end (Appendix A.2): the outgoing
+// current is updated photon by photon with fvoxx0 (Appendix B.3.3) and closed
+// on the u spinor with iovxx0 (Appendix B.3.1).  Chains that share their first
+// j photons share their first j currents, so the orderings are visited as a
+// depth-first walk of the tree of ordered prefixes: a node at depth j holds the
+// current after j photons; it has one child per photon not yet used; the n!
+// leaves close the chain.  Per helicity this costs sum_{j=1}^{n-1} n!/(n-j)!
+// current updates and n! closings instead of (n-1) n! updates.
+//
+// Reductions of the HELAS 4-spinor algebra used here (all exact):
+//  * Massless fermions keep their chirality along the line, so only one
+//    2-component block of the 4-spinor is ever non-zero.  Quark helicities
+//    h_u = h_ubar vanish identically.  Of the two non-vanishing pairs this
+//    code evaluates (h_u, h_ubar) = (-1, +1): the ubar current lives in the
+//    lower block (fvoxx0 outputs 3-4, coupling gal[0]) and closes on the upper
+//    block of u.  The other pair is its parity image, |M(-h,-lam)| = |M(h,lam)|
+//    pointwise for a vector coupling, so the helicity sum is twice the sum over
+//    this block's 2^n photon helicities.
+//  * For an outgoing photon the polarisation vxxxx0 of Appendix B.2 is
+//    eps*(k,lam) = (-lam e_theta + i e_phi)/sqrt(2) with eps^0 = 0.  Its
+//    2x2 vertex block sl = V g (fvoxx0 sl1, sl2) is
+//        V = [[ a3, beta ], [ gamma, -a3 ]],  a3 = eps^3,
+//        beta = eps^1 + i eps^2,  gamma = eps^1 - i eps^2,
+//    and with light-cone components k+ = E + kz, k- = E - kz, kappa = kx + i ky,
+//        sqrt(2) E pT V(+1) = [[ k+k-, -k+ kappa ], [ k- conj(kappa), -k+k- ]]
+//        sqrt(2) E pT V(-1) = [[ -k+k-, -k- kappa ], [ k+ conj(kappa), k+k- ]].
+//    The tree builds V = t V' from the momentum and t ~ 1/(sqrt(2) E pT)
+//    rounded to the working precision; every diagram contains each photon
+//    once, so the exact factor (1/(sqrt(2) E pT t))^2 per photon is applied
+//    to |M|^2 in FP64 at the end and the rounding of t cancels.
+//  * The ubar spinor of oxxxx2 is (0, 0, -sqrt(2 E2), 0) and the u spinor of
+//    ixxxx1 is (0, sqrt(E1 + p1z), 0, 0); their sizes are pulled out too, so
+//    the chain starts at g = (1, 0) and closes with amp = gamma g2 - a3 g3.
+//  * Current update (fvoxx0, lower block): with q the momentum after adding k
+//    and d = -1/q^2,
+//        sl1 = a3 g2 + beta g3,     sl2 = gamma g2 - a3 g3,
+//        g2' = d [ q- sl1 - (qx + i qy) sl2 ],
+//        g3' = d [ q+ sl2 - (qx - i qy) sl1 ].
+//    q starts at -p2 (HELAS stores the ubar momentum times nSF = -1).
+//  * Momenta are scaled by an exact power of two 2^-m with 2^m ~ E1 + E2, so
+//    FP32 values stay near 1; |M(p)|^2 = 2^(2m(2-n)) |M(2^-m p)|^2.
+//
+// Tree layout on the device.  The bottom MB levels of the tree (the subtree
+// below a node with MB photons left) are unrolled at compile time with the
+// remaining photons held in registers ("slots"), so their indices are
+// constants.  The top n-MB levels walk the remaining-photon bitmask with a
+// wave-uniform loop; photon data for those levels sit in LDS as
+// [field][photon][lane] and are read with a wave-uniform photon index.  H
+// helicity configurations ("variants") share each walk, which amortises the
+// momentum part of every node (q update, q^2, 1/q^2) and the walk itself.
+// All control flow is uniform across the wave: lanes only differ in data.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace heget {
+
+// Light-cone momentum: p = E + z, m = E - z, x, y; for photons t is the
+// vertex normalisation ~ 1/(sqrt(2) E pT) (unused for internal momenta).
+template <typename R>
+struct LMom {
+    R p, m, x, y, t;
+};
+
+// Chain currents (g2, g3) for H helicity variants.
+template <typename R, int H>
+struct Chain {
+    R g2r[H], g2i[H], g3r[H], g3i[H];
+};
+
+// Vertex block V' = [[a3, beta], [gamma, -a3]] for H variants.
+template <typename R, int H>
+struct Vert {
+    R a3[H], br[H], bi[H], gr[H], gi[H];
+};
+
+template <int H>
+struct Acc {
+    double re[H], im[H];
+};
+
+template <typename R, int H, int NS>
+struct Slots {
+    LMom<R> k[NS];
+    Vert<R, H> v[NS];
+};
+
+// V'(lam) of photon j for the H variants whose helicity configurations are
+// cfg0 .. cfg0+H-1 (bit j set = helicity +1).  cfg0 is wave-uniform.
+template <typename R, int H>
+__device__ __forceinline__ Vert<R, H> make_vert(const LMom<R> &k, uint32_t cfg0, int j)
+{
+    Vert<R, H> v;
+    const R tp = k.t * k.p, tm = k.t * k.m;
+    const R a3 = tp * k.m;  // t pT^2
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const bool plus = ((cfg0 + h) >> j) & 1u;
+        const R cb = plus ? tp : tm;  // coefficient of -kappa in beta
+        const R cg = plus ? tm : tp;  // coefficient of conj(kappa) in gamma
+        v.a3[h] = plus ? a3 : -a3;
+        v.br[h] = -cb * k.x;
+        v.bi[h] = -cb * k.y;
+        v.gr[h] = cg * k.x;
+        v.gi[h] = -cg * k.y;
+    }
+    return v;
+}
+
+// -1/x: one v_rcp_f32 (1 ulp) in FP32; in FP64 v_rcp_f64 refined by two
+// Newton steps r <- r + r (1 - x r), which restores full double precision.
+__device__ __forceinline__ float neg_recip(float x) { return -__builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ double neg_recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return -r;
+}
+
+// Momentum part of a node: q' = q + k, and d * (q'-, q'+, q'x, q'y), d = -1/q'^2.
+template <typename R>
+struct Prop {
+    R m, p, x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ Prop<R> propagate(const LMom<R> &q, const LMom<R> &k, LMom<R> &qn)
+{
+    qn.p = q.p + k.p;
+    qn.m = q.m + k.m;
+    qn.x = q.x + k.x;
+    qn.y = q.y + k.y;
+    qn.t = R(0);
+    const R q2 = qn.p * qn.m - qn.x * qn.x - qn.y * qn.y;
+    const R d = neg_recip(q2);
+    return {d * qn.m, d * qn.p, d * qn.x, d * qn.y};
+}
+
+// One fvoxx0 current update for every variant.
+template <typename R, int H>
+__device__ __forceinline__ void update(const Vert<R, H> &v, const Chain<R, H> &c, const Prop<R> &P,
+                                       Chain<R, H> &o)
+{
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const R s1r = v.a3[h] * c.g2r[h] + v.br[h] * c.g3r[h] - v.bi[h] * c.g3i[h];
+        const R s1i = v.a3[h] * c.g2i[h] + v.br[h] * c.g3i[h] + v.bi[h] * c.g3r[h];
+        const R s2r = v.gr[h] * c.g2r[h] - v.gi[h] * c.g2i[h] - v.a3[h] * c.g3r[h];
+        const R s2i = v.gr[h] * c.g2i[h] + v.gi[h] * c.g2r[h] - v.a3[h] * c.g3i[h];
+        o.g2r[h] = P.m * s1r - P.x * s2r + P.y * s2i;
+        o.g2i[h] = P.m * s1i - P.x * s2i - P.y * s2r;
+        o.g3r[h] = P.p * s2r - P.x * s1r - P.y * s1i;
+        o.g3i[h] = P.p * s2i - P.x * s1i + P.y * s1r;
+    }
+}
+
+// Closing vertex (iovxx0 with the u spinor): amp = gamma g2 - a3 g3, summed in FP64.
+template <typename R, int H>
+__device__ __forceinline__ void close_chain(const Vert<R, H> &v, const Chain<R, H> &c, Acc<H> &acc)
+{
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const R ar = v.gr[h] * c.g2r[h] - v.gi[h] * c.g2i[h] - v.a3[h] * c.g3r[h];
+        const R ai = v.gr[h] * c.g2i[h] + v.gi[h] * c.g2r[h] - v.a3[h] * c.g3i[h];
+        acc.re[h] += static_cast<double>(ar);
+        acc.im[h] += static_cast<double>(ai);
+    }
+}
+
+// Compile-time loop over the set bits of MASK, calling f(integral_constant<int, bit>).
+template <unsigned MASK, int BIT = 0, typename F>
+__device__ __forceinline__ void for_each_bit(F &&f)
+{
+    if constexpr (MASK != 0u) {
+        if constexpr ((MASK & 1u) != 0u) f(std::integral_constant<int, BIT>{});
+        for_each_bit<(MASK >> 1), BIT + 1>(static_cast<F &&>(f));
+    }
+}
+
+// Unrolled subtree over the slot photons in MASK, entered with current c at momentum q.
+template <typename R, int H, int NS, unsigned MASK>
+__device__ __forceinline__ void subtree(const Slots<R, H, NS> &S, const Chain<R, H> &c,
+                                        const LMom<R> &q, Acc<H> &acc)
+{
+    if constexpr (__builtin_popcount(MASK) == 1) {
+        close_chain<R, H>(S.v[__builtin_ctz(MASK)], c, acc);
+    } else {
+        for_each_bit<MASK>([&](auto bit) {
+            constexpr int s = decltype(bit)::value;
+            LMom<R> qn;
+            const Prop<R> P = propagate<R>(q, S.k[s], qn);
+            Chain<R, H> cn;
+            update<R, H>(S.v[s], c, P, cn);
+            subtree<R, H, NS, (MASK & ~(1u << s))>(S, cn, qn, acc);
+        });
+    }
+}
+
+// LDS photon table of one wave: [field 0..4][photon][lane] = (k+, k-, kx, ky, t).
+constexpr int kPhotonFields = 5;
+
+template <typename R, int N>
+__device__ __forceinline__ LMom<R> lds_photon(const R *tab, int j, int lane)
+{
+    const R *b = tab + j * 64 + lane;
+    return {b[0], b[N * 64], b[2 * N * 64], b[3 * N * 64], b[4 * N * 64]};
+}
+
+// Wave-uniform walk of the top n-MB levels.  `rem` = photons not yet used.
+template <typename R, int N, int MB, int H, int DEPTH>
+__device__ __forceinline__ void top_levels(const R *tab, int lane, uint32_t rem, uint32_t cfg0,
+                                           const Chain<R, H> &c, const LMom<R> &q, Acc<H> &acc)
+{
+    for (uint32_t left = rem; left != 0u; left &= left - 1u) {
+        const int j = __builtin_ctz(left);
+        const LMom<R> k = lds_photon<R, N>(tab, j, lane);
+        const Vert<R, H> v = make_vert<R, H>(k, cfg0, j);
+        LMom<R> qn;
+        const Prop<R> P = propagate<R>(q, k, qn);
+        Chain<R, H> cn;
+        update<R, H>(v, c, P, cn);
+        const uint32_t rest = rem & ~(1u << j);
+        if constexpr (N - DEPTH - 1 == MB) {
+            Slots<R, H, MB> S;
+            uint32_t m = rest;
+#pragma unroll
+            for (int s = 0; s < MB; ++s) {
+                const int js = __builtin_ctz(m);
+                m &= m - 1u;
+                S.k[s] = lds_photon<R, N>(tab, js, lane);
+                S.v[s] = make_vert<R, H>(S.k[s], cfg0, js);
+            }
+            subtree<R, H, MB, (1u << MB) - 1u>(S, cn, qn, acc);
+        } else {
+            top_levels<R, N, MB, H, DEPTH + 1>(tab, lane, rest, cfg0, cn, qn, acc);
+        }
+    }
+}
+
+// Per-point inputs after the FP64 set-up.
+template <typename R, int N>
+struct PointIn {
+    LMom<R> k[N];   // scaled photon momenta
+    LMom<R> q0;     // -p2, scaled
+};
+
+// Sum over helicity passes [pass0, pass1) of |ordering sum|^2 (scaled units,
+// without the external normalisations).  Each pass covers H configurations.
+template <typename R, int N, int MB, int H>
+__device__ __forceinline__ double tree_sum(const PointIn<R, N> &in, R *tab, int lane, int pass0,
+                                           int pass1)
+{
+    double total = 0.0;
+    Chain<R, H> c0;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        c0.g2r[h] = R(1);
+        c0.g2i[h] = R(0);
+        c0.g3r[h] = R(0);
+        c0.g3i[h] = R(0);
+    }
+    for (int pass = pass0; pass < pass1; ++pass) {
+        const uint32_t cfg0 = static_cast<uint32_t>(pass) * H;
+        Acc<H> acc;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            acc.re[h] = 0.0;
+            acc.im[h] = 0.0;
+        }
+        if constexpr (N <= MB) {
+            Slots<R, H, N> S;
+#pragma unroll
+            for (int s = 0; s < N; ++s) {
+                S.k[s] = in.k[s];
+                S.v[s] = make_vert<R, H>(in.k[s], cfg0, s);
+            }
+            subtree<R, H, N, (1u << N) - 1u>(S, c0, in.q0, acc);
+        } else {
+            top_levels<R, N, MB, H, 0>(tab, lane, (1u << N) - 1u, cfg0, c0, in.q0, acc);
+        }
+#pragma unroll
+        for (int h = 0; h < H; ++h) total += acc.re[h] * acc.re[h] + acc.im[h] * acc.im[h];
+    }
+    return total;
+}
+
+}  // namespace heget

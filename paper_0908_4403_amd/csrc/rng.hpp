@@ -1,0 +1,59 @@
+// Counter-based random numbers on the device: Philox4x32-10 (Salmon, Moraes,
+// Dror, Shaw, SC'11).  One call maps (counter, key) to four 32-bit words with
+// ten rounds of two 32x32->64 multiplies; the key is bumped by the Weyl
+// constants between rounds.  Stateless, so any point can be regenerated from
+// its index alone.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace heget {
+
+struct Words4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hiA = __umulhi(kMulA, c0), loA = kMulA * c0;
+        const uint32_t hiB = __umulhi(kMulB, c2), loB = kMulB * c2;
+        const uint32_t t0 = hiB ^ c1 ^ k0;
+        const uint32_t t2 = hiA ^ c3 ^ k1;
+        c0 = t0;
+        c1 = loB;
+        c2 = t2;
+        c3 = loA;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// Uniform in (0,1) from 53 bits of the 64-bit word (hi:lo): (w >> 11 + 1/2) 2^-53.
+__device__ __forceinline__ double open_unit(uint32_t lo, uint32_t hi)
+{
+    const uint64_t w = (static_cast<uint64_t>(hi) << 32) | lo;
+    return (static_cast<double>(w >> 11) + 0.5) * 0x1.0p-53;
+}
+
+// Two uniforms for (seed, point, block, stream).  Counter = {lo(point),
+// hi(point), block, stream}, key = {lo(seed), hi(seed)}.  Stream 0 feeds the
+// photons (blocks 2i, 2i+1 for photon i); stream 1 feeds the partonic
+// kinematics (block 0: parton momentum fractions, block 1: sqrt(shat)).
+__device__ __forceinline__ void uniform_pair(uint64_t seed, uint64_t point, uint32_t block,
+                                             uint32_t stream, double &u0, double &u1)
+{
+    const Words4 r = philox4x32_10(static_cast<uint32_t>(point),
+                                   static_cast<uint32_t>(point >> 32), block, stream,
+                                   static_cast<uint32_t>(seed),
+                                   static_cast<uint32_t>(seed >> 32));
+    u0 = open_unit(r.w0, r.w1);
+    u1 = open_unit(r.w2, r.w3);
+}
+
+}  // namespace heget

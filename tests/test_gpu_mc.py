@@ -1,0 +1,119 @@
+"""GPU parity of the Monte-Carlo side: phase-space generation (Philox +
+RAMBO + cuts) against the oracle's generator on the same counters, and the
+cross section against the oracle's on the same sample.
+
+Floating point decides an integer here (the cut decision); both sides take it
+in FP64, and a mismatch is only accepted for a point whose cut variables lie
+within 1e-9 (relative) of a bound.  sigma: same sample, <= 1e-5 relative
+(FP64 amplitudes: <= 1e-10).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0908_4403_amd as H
+    return H
+
+
+def near_cut(k, pt_min, eta_max, dr_min, tol=1e-9):
+    pt = np.hypot(k[:, 1], k[:, 2])
+    pabs = np.sqrt(pt ** 2 + k[:, 3] ** 2)
+    eta = np.arctanh(k[:, 3] / pabs)
+    phi = np.arctan2(k[:, 2], k[:, 1])
+    if np.any(np.abs(pt / pt_min - 1) < tol) or np.any(np.abs(np.abs(eta) / eta_max - 1) < tol):
+        return True
+    n = k.shape[0]
+    for i in range(n):
+        for j in range(i + 1, n):
+            dphi = abs(phi[i] - phi[j])
+            dphi = 2 * math.pi - dphi if dphi > math.pi else dphi
+            if abs(math.hypot(eta[i] - eta[j], dphi) / dr_min - 1) < tol:
+                return True
+    return False
+
+
+@pytest.mark.parametrize("n,sqrt_s,seed", [(2, 500.0, 0), (4, 1000.0, 1), (8, 2000.0, 4)])
+def test_gen_points_match_oracle(H, orc, n, sqrt_s, seed):
+    N = 3000 + 17
+    mom, w = H.gen_points(n, sqrt_s, (20.0, 2.5, 0.4), seed, N)
+    ref = orc.cm_events(n, sqrt_s, seed, 0, N)
+    assert np.allclose(mom, ref, rtol=0, atol=1e-12 * sqrt_s)
+    vol = orc.rambo_weight(n, sqrt_s ** 2)
+    mismatches = 0
+    for i in range(N):
+        acc = orc.pass_cuts(ref[i, 2:], 0.0, 20.0, 2.5, 0.4)
+        if (w[i] > 0) != acc:
+            assert near_cut(ref[i, 2:], 20.0, 2.5, 0.4), i
+            mismatches += 1
+        elif acc:
+            assert w[i] == pytest.approx(vol, rel=1e-13)
+    assert mismatches <= 1
+
+
+def test_gen_points_device_offsets(H, orc):
+    import torch
+    n, N, first = 3, 1000, 12345
+    mom = torch.empty(((n + 2) * 4, N), dtype=torch.float64, device="cuda")
+    w = torch.empty(N, dtype=torch.float64, device="cuda")
+    H.gen_points_device(n, 800.0, mom, w, (20.0, 2.5, 0.4), 9, first)
+    torch.cuda.synchronize()
+    got = mom.cpu().numpy().T.reshape(N, n + 2, 4)
+    ref = orc.cm_events(n, 800.0, 9, first, N)
+    assert np.allclose(got, ref, rtol=0, atol=1e-12 * 800.0)
+
+
+def _cfgs(H, orc, mode, **kw):
+    return H.Config(mode=mode, **kw), orc.Config(mode=mode, **{k: v for k, v in kw.items() if k != "prec"})
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+def test_xsec_config1_matches_oracle_and_closed_form(H, orc, prec):
+    import pins
+    kw = dict(seed=0, npoints=16384, sqrt_s=500.0, pt_min=20.0, eta_max=2.5, dr_min=0.0)
+    hc, oc = _cfgs(H, orc, H.FIXED_SHAT, prec=getattr(H, prec), **kw)
+    got = H.xsec(2, hc)
+    want = orc.xsec(2, oc)
+    assert got["n_gen"] == want["n_gen"] and got["n_acc"] == want["n_acc"]
+    tol = 1e-10 if prec == "FP64" else 1e-5
+    assert abs(got["sigma_fb"] / want["sigma_fb"] - 1) < tol
+    assert abs(got["err_fb"] / want["err_fb"] - 1) < 1e-4
+    closed = pins.sigma_hat_n2(500.0 ** 2, 1 / 137, 2 / 3, pins.cos_max_n2(500.0, 0.0, 20.0, 2.5))
+    assert abs(got["sigma_fb"] - closed) < 3.5 * got["err_fb"]
+
+
+@pytest.mark.parametrize("n,mode,extra,npoints", [
+    (3, "FIXED_SHAT", dict(sqrt_s=1000.0), 3000),
+    (4, "FIXED_SHAT", dict(sqrt_s=1000.0), 1200),
+    (3, "UNIFORM_SQRTSHAT", dict(sqrt_shat_lo=200.0, sqrt_shat_hi=2000.0), 3000),
+    (3, "PP_TOY", dict(sqrt_s=14000.0, sqrt_shat_lo=150.0), 6000),
+    (5, "PP_TOY", dict(sqrt_s=14000.0, sqrt_shat_lo=150.0), 1500),
+])
+def test_xsec_matches_oracle_same_sample(H, orc, n, mode, extra, npoints):
+    kw = dict(seed=3, npoints=npoints, pt_min=20.0, eta_max=2.5, dr_min=0.4, **extra)
+    for prec, tol in (("FP64", 1e-10), ("FP32", 1e-5)):
+        hc, oc = _cfgs(H, orc, getattr(H, mode), prec=getattr(H, prec), **kw)
+        got = H.xsec(n, hc)
+        want = orc.xsec(n, oc)
+        print(mode, n, prec, got["sigma_fb"], want["sigma_fb"], got["n_acc"], flush=True)
+        assert got["n_acc"] == want["n_acc"]
+        assert abs(got["sigma_fb"] / want["sigma_fb"] - 1) < tol
+
+
+def test_xsec_deterministic_and_empty(H):
+    cfg = H.Config(prec=H.FP32, seed=5, npoints=50000 + 3, sqrt_s=1000.0)
+    a = H.xsec(4, cfg)
+    b = H.xsec(4, cfg)
+    assert a == b
+    z = H.xsec(4, H.Config(prec=H.FP32, npoints=0, sqrt_s=1000.0))
+    assert z["n_gen"] == 0 and z["sigma_fb"] == 0.0
