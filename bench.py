@@ -38,9 +38,9 @@ sys.path.insert(0, ROOT)
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PUBLISHED_FP32_VECTOR_TFLOPS = 157.3
 
-WORKLOADS = {
-    "uubar_4a_1TeV_2p20": dict(n=4, sqrt_s=1000.0, npoints=1 << 20, seed=1),
-}
+def _workloads():
+    from paper_0908_4403_amd.workloads import MIXED_BATCH, WORKLOADS
+    return WORKLOADS, MIXED_BATCH
 
 
 def run_steps(H, torch, n, cfg, steps, warmup):
@@ -60,6 +60,37 @@ def run_steps(H, torch, n, cfg, steps, warmup):
     return (t1 - t0) * 1e3 / steps, me2_ms / max(launches, 1), launches, res[0]
 
 
+def mixed_batch(H, torch, prec, steps):
+    """n = 2..7 with 2^22..2^17 points, sqrt(shat) uniform in [200 GeV, 2 TeV]:
+    one heget_xsec_batch (persistent amplitude launch, graph-captured) against
+    one heget_xsec call per n."""
+    _, mixed = _workloads()
+    ns = [s["n"] for s in mixed]
+    cfgs = [H.Config(mode=s["mode"], prec=prec, seed=s["seed"], npoints=s["npoints"],
+                     sqrt_shat_lo=s["lo"], sqrt_shat_hi=s["hi"], pt_min=s["cuts"][0],
+                     eta_max=s["cuts"][1], dr_min=s["cuts"][2]) for s in mixed]
+    res = H.xsec_batch(ns, cfgs)  # capture + warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        H.xsec_batch(ns, cfgs)
+    t_batch = (time.perf_counter() - t0) / steps
+    for n, c in zip(ns, cfgs):
+        H.xsec(n, c)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for n, c in zip(ns, cfgs):
+            H.xsec(n, c)
+    t_single = (time.perf_counter() - t0) / steps
+    acc = sum(r["n_acc"] for r in res)
+    gen = sum(c.npoints for c in cfgs)
+    return {"workload": "mixed n=2..7, 2^22..2^17 points, sqrt(shat) uniform in [200, 2000] GeV",
+            "points_generated": gen, "points_evaluated": acc,
+            "batch_ms": t_batch * 1e3, "one_launch_per_n_ms": t_single * 1e3,
+            "batch_points_per_s": acc / t_batch, "speedup_vs_per_n": t_single / t_batch,
+            "sigma_fb": {str(n): r["sigma_fb"] for n, r in zip(ns, res)}}
+
+
 def cpu_baseline(n, wl, budget_s):
     """FP64 oracle |M|^2 on the first survivors of the same stream (~budget_s of CPU)."""
     import numpy as np
@@ -70,7 +101,7 @@ def cpu_baseline(n, wl, budget_s):
         while len(out) < count:
             ev = O.cm_events(n, wl["sqrt_s"], wl["seed"], start, 4 * count)
             start += ev.shape[0]
-            out.extend(p for p in ev if O.pass_cuts(p[2:], 0.0, 20.0, 2.5, 0.4))
+            out.extend(p for p in ev if O.pass_cuts(p[2:], 0.0, *wl["cuts"]))
         return np.array(out[:count])
 
     cal = sample(256)
@@ -92,9 +123,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="uubar_4a_1TeV_2p20", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="uubar_4a_1TeV_2p20")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed n=2..7 batch")
+    ap.add_argument("--no-tune", action="store_true", help="use the untuned kernel shapes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the |M|^2 path "
@@ -104,11 +137,18 @@ def main():
     import torch
     import paper_0908_4403_amd as H
 
-    wl = WORKLOADS[args.workload]
+    workloads, _ = _workloads()
+    wl = workloads[args.workload]
     n = wl["n"]
     torch.cuda.set_device(0)
-    base = dict(mode=H.FIXED_SHAT, seed=wl["seed"], npoints=wl["npoints"], sqrt_s=wl["sqrt_s"],
-                pt_min=20.0, eta_max=2.5, dr_min=0.4)
+    base = dict(mode=wl["mode"], seed=wl["seed"], npoints=wl["npoints"], sqrt_s=wl["sqrt_s"],
+                sqrt_shat_lo=wl.get("lo", 0.0), sqrt_shat_hi=wl.get("hi", 0.0),
+                pt_min=wl["cuts"][0], eta_max=wl["cuts"][1], dr_min=wl["cuts"][2])
+    tuned = {}
+    if not args.no_tune:
+        for prec, name in ((H.FP32, "fp32"), (H.FP64, "fp64")):
+            tuned[name] = H.autotune(n, prec, min(wl["npoints"], 1 << 18))
+        print(f"bench: tuned shapes {tuned}", file=sys.stderr, flush=True)
 
     print(f"bench: {args.workload} FP32 steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
     ms32, k32, l32, r32 = run_steps(H, torch, n, H.Config(prec=H.FP32, **base), args.steps, args.warmup)
@@ -122,6 +162,13 @@ def main():
     f64 = H.me2_flops(n, H.FP64)[0]
     ach32 = f32 * n_acc / (k32 * 1e-3) / 1e12
     ach64 = f64 * n_acc / (k64 * 1e-3) / 1e12
+
+    mixed = None
+    if not args.no_mixed:
+        print("bench: mixed n=2..7 batch", file=sys.stderr, flush=True)
+        mixed = mixed_batch(H, torch, H.FP32, 3)
+        print(f"bench: mixed batch {mixed['batch_ms']:.2f} ms vs per-n {mixed['one_launch_per_n_ms']:.2f} ms",
+              file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -144,7 +191,7 @@ def main():
         "config": {"workload": args.workload, "process": f"u ubar -> {n} photons",
                    "sqrt_shat_GeV": wl["sqrt_s"], "points_generated": wl["npoints"],
                    "points_evaluated": n_acc, "seed": wl["seed"],
-                   "cuts": "pT>20 GeV, |eta|<2.5, dR>0.4", "sigma_fb": r32["sigma_fb"],
+                   "cuts": "pT>%g GeV, |eta|<%g, dR>%g" % tuple(wl["cuts"]), "sigma_fb": r32["sigma_fb"],
                    "sigma_err_fb": r32["err_fb"]},
         "roofline": {"bound": "alu", "achieved": ach32, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": ach32 / PEAK_VALU_TFLOPS, "traffic": None,
@@ -155,6 +202,8 @@ def main():
                        "sigma_fb": r64["sigma_fb"], "flops_per_point": f64},
         "fp32_over_fp64": (n_acc / ms32) / (r64["n_acc"] / ms64),
         "generated_points_per_s": wl["npoints"] / (ms32 * 1e-3),
+        "tuned_shapes": tuned,
+        "mixed_batch": mixed,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -135,6 +135,19 @@ heget_status heget_xsec(int n, const heget_config *cfg, heget_result *out);
 heget_status heget_xsec_async(int n, const heget_config *cfg, heget_result *out,
                               heget_stream stream);
 
+/* Several cross sections in one device pass (e.g. n = 2..7 with different
+ * point counts): generation, cuts and compaction per configuration, then ONE
+ * persistent amplitude launch whose waves pull (configuration, 64-point tile,
+ * helicity chunk) work items from an atomic queue, most expensive items
+ * first, then the per-configuration reductions.  The whole sequence is
+ * captured in a hipGraph on first use and replayed for the same arguments.
+ * n[ncfg], cfgs[ncfg] (in, host), out[ncfg] (out, host); 1 <= ncfg <= 8, all
+ * with the same prec.  Results equal heget_xsec per configuration up to the
+ * rounding of the helicity-chunk grouping.  Set HEGET_NO_GRAPH=1 in the
+ * environment to launch without graph capture. */
+heget_status heget_xsec_batch(const int *n, const heget_config *cfgs, int ncfg,
+                              heget_result *out);
+
 /* Couplings used by heget_me2 / heget_me2_device (defaults: 1/137, 2/3). */
 heget_status heget_set_couplings(double alpha, double charge);
 
@@ -153,6 +166,28 @@ heget_status heget_timing_read(double *me2_ms, int64_t *me2_launches, int reset)
  * unrolled depth and the helicities per walk of that kernel (may be NULL). */
 heget_status heget_me2_flops(int n, heget_prec prec, double *flops_per_point, int *unrolled,
                              int *helicities_per_walk);
+
+/* Autotuner.  Times every compiled shape of the amplitude kernel for (n,
+ * prec) -- unrolled depth of the ordering tree, helicities per tree walk,
+ * waves per workgroup -- on npoints synthetic points (sqrt(shat) = 1 TeV)
+ * generated on the device, and makes the fastest the shape every later call
+ * uses for (n, prec) in this process.  If HEGET_TUNING_CACHE names a file,
+ * the choice is also written there (one JSON object per line) and read back
+ * by later processes on first device use.  Outputs (host, may be NULL): the
+ * chosen shape and its time per launch in ms.  64 <= npoints < 2^31. */
+heget_status heget_autotune(int n, heget_prec prec, int64_t npoints, int *unrolled,
+                            int *helicities_per_walk, int *waves_per_block, double *ms);
+
+/* The compiled shapes for (n, prec), the one in use first: mb[i] (unrolled
+ * depth), h[i] (helicities per walk), wpb[i] (waves per block) for i < max
+ * (arrays may be NULL when max = 0); *count receives the number of shapes. */
+heget_status heget_kernel_shapes(int n, heget_prec prec, int max, int *mb, int *h, int *wpb,
+                                 int *count);
+
+/* Use the compiled shape (mb, h, wpb) for (n, prec) from now on in this
+ * process; (0, 0, 0) restores the default.  HEGET_ERR_ARG if no such shape
+ * was compiled (heget_kernel_shapes lists them). */
+heget_status heget_set_kernel_shape(int n, heget_prec prec, int mb, int h, int wpb);
 
 /* Message of the last failure on this thread ("" if none). */
 const char *heget_last_error(void);

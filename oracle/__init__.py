@@ -29,7 +29,7 @@ class OrcConfig(C.Structure):
                 ("first_point", C.c_int64), ("sqrt_s", C.c_double),
                 ("sqrt_shat_lo", C.c_double), ("sqrt_shat_hi", C.c_double),
                 ("pt_min", C.c_double), ("eta_max", C.c_double), ("dr_min", C.c_double),
-                ("alpha", C.c_double), ("charge", C.c_double)]
+                ("alpha", C.c_double), ("charge", C.c_double), ("me2_method", C.c_int)]
 
 
 class OrcResult(C.Structure):
@@ -236,11 +236,12 @@ class Config:
     dr_min: float = 0.4
     alpha: float = ALPHA
     charge: float = CHARGE_U
+    me2_method: int = 0  # 0: ordering sum, 1: subset recursion
 
     def c(self) -> OrcConfig:
         return OrcConfig(self.mode, self.seed, self.npoints, self.first_point, self.sqrt_s,
                          self.sqrt_shat_lo, self.sqrt_shat_hi, self.pt_min, self.eta_max,
-                         self.dr_min, self.alpha, self.charge)
+                         self.dr_min, self.alpha, self.charge, self.me2_method)
 
 
 def point(n: int, cfg: Config, i: int):

@@ -590,6 +590,12 @@ static double partonic_factor(int n, double shat)
            orc_rambo_weight(n, shat) * orc_gev2_fb();
 }
 
+static double point_me2(int n, const orc_config *cfg, const double *p, int u_minus_z)
+{
+    if (cfg->me2_method == 1 && !u_minus_z) return orc_me2_subsets(n, p, cfg->alpha, cfg->charge);
+    return orc_me2(n, p, cfg->alpha, cfg->charge, 1, u_minus_z);
+}
+
 int orc_point(int n, const orc_config *cfg, uint64_t point, double *p, double *y,
               double *me2, double *w)
 {
@@ -622,7 +628,7 @@ int orc_point(int n, const orc_config *cfg, uint64_t point, double *p, double *y
     double base = partonic_factor(n, shat);
     if (cfg->mode != ORC_PP_TOY) {
         if (!orc_pass_cuts(n, p + 8, 0.0, cfg->pt_min, cfg->eta_max, cfg->dr_min)) return 0;
-        *me2 = orc_me2(n, p, cfg->alpha, cfg->charge, 1, 0);
+        *me2 = point_me2(n, cfg, p, 0);
         *w = base * *me2;
         return 1;
     }
@@ -642,8 +648,8 @@ int orc_point(int n, const orc_config *cfg, uint64_t point, double *p, double *y
     }
     int passA = orc_pass_cuts(n, p + 8, yA, cfg->pt_min, cfg->eta_max, cfg->dr_min);
     int passB = orc_pass_cuts(n, pB + 8, yB, cfg->pt_min, cfg->eta_max, cfg->dr_min);
-    double meA = passA ? orc_me2(n, p, cfg->alpha, cfg->charge, 1, 0) : 0.0;
-    double meB = passB ? orc_me2(n, pB, cfg->alpha, cfg->charge, 1, 1) : 0.0;
+    double meA = passA ? point_me2(n, cfg, p, 0) : 0.0;
+    double meB = passB ? point_me2(n, cfg, pB, 1) : 0.0;
     *me2 = passA ? meA : meB;
     *w = fpdf * base * (meA + meB);
     return passA || passB;

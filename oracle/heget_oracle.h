@@ -108,6 +108,7 @@ typedef struct {
     double sqrt_shat_lo, sqrt_shat_hi; /* uniform range; PP: lo = min sqrt(shat) */
     double pt_min, eta_max, dr_min;
     double alpha, charge;
+    int me2_method;      /* 0: sum over orderings (orc_me2); 1: subset recursion */
 } orc_config;
 
 typedef struct {

@@ -32,8 +32,11 @@ FP64, FP32 = 0, 1
 FIXED_SHAT, UNIFORM_SQRTSHAT, PP_TOY = 0, 1, 2
 
 EXPORTS = ["heget_gen_points", "heget_gen_points_device", "heget_me2", "heget_me2_device",
-           "heget_xsec", "heget_xsec_async", "heget_set_couplings", "heget_timing_enable",
-           "heget_timing_read", "heget_me2_flops", "heget_last_error", "heget_shutdown"]
+           "heget_xsec", "heget_xsec_async", "heget_xsec_batch", "heget_set_couplings",
+           "heget_timing_enable",
+           "heget_timing_read", "heget_me2_flops", "heget_autotune", "heget_kernel_shapes",
+           "heget_set_kernel_shape",
+           "heget_last_error", "heget_shutdown"]
 
 
 class Cuts(C.Structure):
@@ -65,10 +68,15 @@ _lib.heget_me2.argtypes = [C.c_int, C.c_int64, _dp, _dp, C.c_int]
 _lib.heget_me2_device.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
 _lib.heget_xsec.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result)]
 _lib.heget_xsec_async.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result), C.c_void_p]
+_lib.heget_xsec_batch.argtypes = [C.POINTER(C.c_int), C.POINTER(_Config), C.c_int, C.POINTER(Result)]
 _lib.heget_set_couplings.argtypes = [C.c_double, C.c_double]
 _lib.heget_timing_enable.argtypes = [C.c_int]
 _lib.heget_timing_read.argtypes = [_dp, C.POINTER(C.c_int64), C.c_int]
 _lib.heget_me2_flops.argtypes = [C.c_int, C.c_int, _dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+_ipt = C.POINTER(C.c_int)
+_lib.heget_autotune.argtypes = [C.c_int, C.c_int, C.c_int64, _ipt, _ipt, _ipt, _dp]
+_lib.heget_kernel_shapes.argtypes = [C.c_int, C.c_int, C.c_int, _ipt, _ipt, _ipt, _ipt]
+_lib.heget_set_kernel_shape.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
 _lib.heget_last_error.restype = C.c_char_p
 _lib.heget_shutdown.restype = None
 for _f in EXPORTS[:-2]:
@@ -171,6 +179,17 @@ _MAX_INFLIGHT = 1024
 _inflight: "collections.deque" = None
 
 
+def xsec_batch(ns, cfgs, return_status: bool = False):
+    """Cross sections of several configurations in one device pass (list of dicts)."""
+    k = len(ns)
+    na = (C.c_int * k)(*ns)
+    ca = (_Config * k)(*[c.c() for c in cfgs])
+    ra = (Result * k)()
+    st = _check(_lib.heget_xsec_batch(na, ca, k, ra), "heget_xsec_batch")
+    out = [r.as_dict() for r in ra]
+    return (out, st) if return_status else out
+
+
 class XsecAsync:
     """Handle of an enqueued heget_xsec_async; .result() after the stream completes.
 
@@ -238,6 +257,31 @@ def me2_flops(n: int, prec: int = FP32):
     f, mb, h = C.c_double(), C.c_int(), C.c_int()
     _check(_lib.heget_me2_flops(n, prec, C.byref(f), C.byref(mb), C.byref(h)), "heget_me2_flops")
     return f.value, mb.value, h.value
+
+
+def autotune(n: int, prec: int = FP32, npoints: int = 1 << 18) -> dict:
+    """Time every compiled kernel shape for (n, prec) and keep the fastest."""
+    mb, h, wpb, ms = C.c_int(), C.c_int(), C.c_int(), C.c_double()
+    _check(_lib.heget_autotune(n, prec, npoints, C.byref(mb), C.byref(h), C.byref(wpb), C.byref(ms)),
+           "heget_autotune")
+    return {"unrolled": mb.value, "helicities_per_walk": h.value, "waves_per_block": wpb.value,
+            "ms": ms.value}
+
+
+def kernel_shapes(n: int, prec: int = FP32):
+    """[(unrolled depth, helicities per walk, waves per block)], the shape in use first."""
+    cnt = C.c_int()
+    _check(_lib.heget_kernel_shapes(n, prec, 0, None, None, None, C.byref(cnt)), "heget_kernel_shapes")
+    k = cnt.value
+    mb, h, wpb = (C.c_int * k)(), (C.c_int * k)(), (C.c_int * k)()
+    _check(_lib.heget_kernel_shapes(n, prec, k, mb, h, wpb, C.byref(cnt)), "heget_kernel_shapes")
+    return list(zip(mb, h, wpb))
+
+
+def set_kernel_shape(n: int, prec: int, shape=None) -> None:
+    """Force a compiled shape (unrolled, helicities_per_walk, waves_per_block); None = default."""
+    mb, h, wpb = shape if shape is not None else (0, 0, 0)
+    _check(_lib.heget_set_kernel_shape(n, prec, mb, h, wpb), "heget_set_kernel_shape")
 
 
 def shutdown() -> None:

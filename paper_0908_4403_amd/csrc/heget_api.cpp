@@ -4,7 +4,9 @@
 // mc_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -69,8 +71,28 @@ constexpr int kRing = 256;
 
 enum Slot {
     S_MOM, S_WFAC, S_FLAG, S_BCOUNT, S_OFFS, S_COUNT, S_INDEX, S_PART, S_ME2, S_PARTIALS, S_RES,
-    S_FLAGS, S_OUT, S_NSLOTS
+    S_FLAGS, S_OUT, S_BATCH, S_NSLOTS
 };
+
+// Captured mixed-n batches, keyed by their configuration; replayed on repeat calls.
+struct BatchGraph {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+    double *staged = nullptr;  // pinned: 4 doubles per slice + flags
+};
+std::vector<BatchGraph> g_graphs;
+
+void drop_graphs()
+{
+    for (BatchGraph &b : g_graphs) {
+        if (b.exec) (void)hipGraphExecDestroy(b.exec);
+        if (b.staged) (void)hipHostFree(b.staged);
+    }
+    g_graphs.clear();
+}
+
+std::string g_arch;
+void load_tuning_cache();
 
 heget_status ensure_device()
 {
@@ -86,7 +108,12 @@ heget_status ensure_device()
                          hipHostMallocDefault));
     g.buf.assign(S_NSLOTS, nullptr);
     g.cap.assign(S_NSLOTS, 0);
+    hipDeviceProp_t prop;
+    HG_HIP(hipGetDeviceProperties(&prop, g.device));
+    g_arch = prop.gcnArchName;
+    g_arch = g_arch.substr(0, g_arch.find(':'));
     g.ready = true;
+    load_tuning_cache();
     return HEGET_OK;
 }
 
@@ -96,6 +123,7 @@ heget_status scratch(int slot, size_t bytes, void **out)
     bytes = bytes < 256 ? 256 : bytes;
     if (g.cap[slot] < bytes) {
         HG_HIP(hipDeviceSynchronize());
+        if (slot == S_BATCH) drop_graphs();
         if (g.buf[slot]) HG_HIP(hipFree(g.buf[slot]));
         g.buf[slot] = nullptr;
         g.cap[slot] = 0;
@@ -195,20 +223,111 @@ double me2_coef(int n, double alpha, double charge)
     return 2.0 * std::pow(e2q2, n);
 }
 
-// Helicity chunks so that enough wave-sized work items exist for small batches.
-int plan_chunks(const heget::Me2Variant &v, int64_t points_expected)
+double me2_flops_per_point(int n, int mb, int h);
+
+// Helicity chunks per work item: enough wave-sized items for small batches
+// (>= 8192), and no item above ~2e8 flops so the tail of a launch stays short.
+int plan_chunks_shape(int n, int mb, int h, int64_t points_expected)
 {
-    const int passes = (1 << v.n) / v.h;
+    const int passes = (1 << n) / h;
     const int64_t tiles = (points_expected + 63) / 64;
-    const int64_t target = 8192;
+    const double item_flops = 64.0 * me2_flops_per_point(n, mb, h);
     int c = 1;
-    while (c < passes && tiles * c < target) c *= 2;
+    while (c < passes && (tiles * c < 8192 || item_flops / c > 2e8)) c *= 2;
     return c;
 }
 
+int plan_chunks(const heget::Me2Variant &v, int64_t points_expected)
+{
+    return plan_chunks_shape(v.n, v.mb, v.h, points_expected);
+}
+
+// Shape chosen by the autotuner (or loaded from the tuning cache) per (prec, n).
+const heget::Me2Variant *g_tuned[2][9] = {};
+
 const heget::Me2Variant *pick_variant(int prec, int n)
 {
+    if (prec >= 0 && prec < 2 && n >= 2 && n <= 8 && g_tuned[prec][n]) return g_tuned[prec][n];
     return heget::me2_default(prec, n);
+}
+
+const heget::Me2Variant *find_variant(int prec, int n, int mb, int h, int wpb)
+{
+    int cnt = 0;
+    const heget::Me2Variant *v = heget::me2_variants(&cnt);
+    for (int i = 0; i < cnt; ++i)
+        if (v[i].prec == prec && v[i].n == n && v[i].mb == mb && v[i].h == h && v[i].wpb == wpb)
+            return &v[i];
+    return nullptr;
+}
+
+// Tuning cache: one JSON object per line,
+// {"arch": "gfx950", "prec": 1, "n": 4, "mb": 4, "h": 2, "wpb": 4, "ms": 0.48, "points": 1048576}
+void load_tuning_cache()
+{
+    const char *path = std::getenv("HEGET_TUNING_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char arch[64] = {0};
+        int prec, n, mb, h, wpb;
+        if (std::sscanf(line, " {\"arch\": \"%63[^\"]\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"wpb\": %d",
+                        arch, &prec, &n, &mb, &h, &wpb) == 6 &&
+            g_arch == arch) {
+            const heget::Me2Variant *v = find_variant(prec, n, mb, h, wpb);
+            if (v) g_tuned[prec][n] = v;
+        }
+    }
+    std::fclose(f);
+}
+
+void save_tuning_cache(const heget::Me2Variant &v, double ms, int64_t points)
+{
+    const char *path = std::getenv("HEGET_TUNING_CACHE");
+    if (!path) return;
+    // keep other entries, replace this (arch, prec, n)
+    std::vector<std::string> keep;
+    if (FILE *f = std::fopen(path, "r")) {
+        char line[512];
+        char tag[128];
+        std::snprintf(tag, sizeof tag, "{\"arch\": \"%s\", \"prec\": %d, \"n\": %d,", g_arch.c_str(), v.prec, v.n);
+        while (std::fgets(line, sizeof line, f))
+            if (std::strncmp(line, tag, std::strlen(tag)) != 0 && line[0] == '{') keep.push_back(line);
+        std::fclose(f);
+    }
+    if (FILE *f = std::fopen(path, "w")) {
+        for (const std::string &l : keep) std::fputs(l.c_str(), f);
+        std::fprintf(f, "{\"arch\": \"%s\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"wpb\": %d, \"ms\": %.6f, \"points\": %lld}\n",
+                     g_arch.c_str(), v.prec, v.n, v.mb, v.h, v.wpb, ms, static_cast<long long>(points));
+        std::fclose(f);
+    }
+}
+
+// Algorithmic flops per point of the tree schedule with unrolled depth mb and
+// h helicities per walk (FMA = 2; add, multiply, reciprocal = 1):
+//   node: q update 4, q^2 5, 1/q^2 1, scale by d 4 (= 14, shared by the walk's
+//         helicities) + per helicity 8 three-term complex products (= 40)
+//   closing: 10 + 2 FP64 adds per helicity
+//   vertex block build: 3 + 4 per helicity
+//   |ordering sum|^2 in FP64: 4 per helicity
+double me2_flops_per_point(int n, int mb, int h)
+{
+    const double H = h;
+    const double walks = double(1 << n) / H;
+    const double nfact = factorial(n);
+    double nodes = 0.0;  // sum_{j=1}^{n-1} n!/(n-j)!
+    for (int j = 1; j <= n - 1; ++j) nodes += nfact / factorial(n - j);
+    double builds = n;   // vertex blocks built per walk
+    if (n > mb) {
+        double top = 0.0;
+        for (int j = 1; j <= n - mb; ++j) top += nfact / factorial(n - j);
+        builds = top + nfact / factorial(mb) * mb;
+    }
+    const double per_walk = nodes * (14.0 + 40.0 * H) + nfact * 12.0 * H + builds * (3.0 + 4.0 * H) +
+                            4.0 * H;
+    return walks * per_walk;
 }
 
 // ---------------------------------------------------------------- timing hooks
@@ -298,21 +417,12 @@ struct XsecTicket {
     int64_t n_gen;
 };
 
+heget_result make_result(const double *st, int64_t n_gen);
+
 void xsec_finish(void *p)
 {
     XsecTicket *t = static_cast<XsecTicket *>(p);
-    const double sum = t->staged[0], comp = t->staged[1], sum2 = t->staged[2];
-    const int64_t N = t->n_gen;
-    heget_result r{};
-    r.sum_w = sum;
-    r.sum_w_comp = comp;
-    r.sum_w2 = sum2;
-    r.n_gen = N;
-    r.n_acc = static_cast<int64_t>(t->staged[3]);
-    r.sigma_fb = N > 0 ? sum / double(N) : 0.0;
-    const double var = N > 1 ? (sum2 / double(N) - r.sigma_fb * r.sigma_fb) / double(N - 1) : 0.0;
-    r.err_fb = std::sqrt(var > 0.0 ? var : 0.0);
-    *t->out = r;
+    *t->out = make_result(t->staged, t->n_gen);
     delete t;
 }
 
@@ -379,6 +489,144 @@ heget_status xsec_enqueue(int n, const heget_config *cfg, heget_result *out, hip
     HG_HIP(hipLaunchHostFunc(s, xsec_finish, t));
     if (flags_out) *flags_out = flags;
     return HEGET_OK;
+}
+
+
+// ---------------------------------------------------------------- mixed-n batch
+
+// Bump allocator over one scratch slot (256-byte aligned pieces).
+struct Arena {
+    char *base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct SliceBufs {
+    double *mom, *wfac, *part, *me2, *partials, *res;
+    uint8_t *flag;
+    int32_t *bcount, *offs, *index;
+    int64_t *d_count;
+    int nb, nchunks, mb, h;
+};
+
+void carve_batch(Arena &ar, int ncfg, const int *n, const heget_config *cfgs, SliceBufs *sb,
+                 unsigned **flags, unsigned long long **queue, int64_t **item_start)
+{
+    *flags = ar.take<unsigned>(1);
+    *queue = ar.take<unsigned long long>(1);
+    *item_start = ar.take<int64_t>(heget::kMaxSlices + 1);
+    for (int s = 0; s < ncfg; ++s) {
+        const int64_t np = cfgs[s].npoints;
+        SliceBufs &b = sb[s];
+        heget::me2_batch_shape(cfgs[s].prec, n[s], &b.mb, &b.h);
+        b.nb = static_cast<int>((np + 255) / 256);
+        b.nchunks = plan_chunks_shape(n[s], b.mb, b.h, np / 2);
+        b.mom = ar.take<double>(size_t(n[s] + 2) * 4 * size_t(np));
+        b.wfac = ar.take<double>(size_t(np));
+        b.flag = ar.take<uint8_t>(size_t(np));
+        b.bcount = ar.take<int32_t>(size_t(b.nb));
+        b.offs = ar.take<int32_t>(size_t(b.nb));
+        b.d_count = ar.take<int64_t>(1);
+        b.index = ar.take<int32_t>(size_t(np));
+        b.part = ar.take<double>(size_t(b.nchunks) * size_t(np));
+        b.me2 = b.nchunks > 1 ? ar.take<double>(size_t(np)) : b.part;
+        b.partials = ar.take<double>(size_t(3) * b.nb);
+        b.res = ar.take<double>(4);
+    }
+}
+
+heget_status batch_enqueue(int ncfg, const int *n, const heget_config *cfgs, SliceBufs *sb,
+                           unsigned *flags, unsigned long long *queue, int64_t *item_start,
+                           double *staged, hipStream_t s)
+{
+    HG_HIP(heget::launch_zero_u32(flags, 1, s));
+    HG_HIP(heget::launch_zero_u32(reinterpret_cast<unsigned *>(queue), 2, s));
+    for (int i = 0; i < ncfg; ++i) {
+        const heget_config &c = cfgs[i];
+        SliceBufs &b = sb[i];
+        heget::GenParams gp{};
+        gp.mode = c.mode;
+        gp.seed = c.seed;
+        gp.npoints = c.npoints;
+        gp.sqrt_s = c.sqrt_s;
+        gp.lo = c.sqrt_shat_lo;
+        gp.hi = c.sqrt_shat_hi;
+        gp.pt_min = c.cuts.pt_min;
+        gp.eta_max = c.cuts.eta_max;
+        gp.dr_min = c.cuts.dr_min;
+        gp.partonic_coef = partonic_coef(n[i]);
+        gp.phase_volume_coef = phase_volume_coef(n[i]);
+        gp.weight_kind = 1;
+        HG_HIP(heget::launch_gen(n[i], gp, b.mom, c.npoints, b.wfac, b.flag, b.bcount, s));
+        HG_HIP(heget::launch_scan(b.bcount, b.nb, b.offs, b.d_count, s));
+        HG_HIP(heget::launch_compact(b.flag, c.npoints, b.offs, b.index, s));
+    }
+    // work items of the most expensive slices first (longest-processing-time order)
+    std::vector<int> order(ncfg);
+    for (int i = 0; i < ncfg; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+        const double cx = me2_flops_per_point(n[x], sb[x].mb, sb[x].h) / sb[x].nchunks;
+        const double cy = me2_flops_per_point(n[y], sb[y].mb, sb[y].h) / sb[y].nchunks;
+        return cx > cy || (cx == cy && x < y);
+    });
+    heget::BatchDesc bd{};
+    bd.nslices = ncfg;
+    bd.item_start = item_start;
+    bd.queue = queue;
+    bd.flags = flags;
+    for (int k = 0; k < ncfg; ++k) {
+        const int i = order[k];
+        const heget_config &c = cfgs[i];
+        bd.s[k] = heget::SliceDesc{sb[i].mom, c.npoints, sb[i].index, sb[i].d_count, sb[i].part,
+                                   c.npoints, me2_coef(n[i], c.alpha, c.charge), n[i],
+                                   sb[i].nchunks};
+    }
+    HG_HIP(heget::launch_batch_plan(bd, s));
+    int cus = 0;
+    HG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g.device));
+    const int grid = cus * heget::me2_batch_blocks_per_cu(cfgs[0].prec);
+    HG_HIP(heget::launch_me2_batch(cfgs[0].prec, bd, grid, s));
+    for (int i = 0; i < ncfg; ++i) {
+        SliceBufs &b = sb[i];
+        const int64_t np = cfgs[i].npoints;
+        if (b.nchunks > 1)
+            HG_HIP(heget::launch_sum_chunks(b.part, b.nchunks, np, b.d_count, np, b.me2, flags, s));
+        HG_HIP(heget::launch_weights(b.me2, b.index, b.wfac, b.d_count, np, b.partials, flags, s));
+        HG_HIP(heget::launch_final(b.partials, b.nb, b.d_count, b.res, s));
+        HG_HIP(hipMemcpyAsync(staged + 4 * i, b.res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HG_HIP(hipMemcpyAsync(staged + 4 * heget::kMaxSlices, flags, sizeof(unsigned),
+                          hipMemcpyDeviceToHost, s));
+    return HEGET_OK;
+}
+
+std::string batch_key(int ncfg, const int *n, const heget_config *cfgs)
+{
+    std::string k(reinterpret_cast<const char *>(n), sizeof(int) * size_t(ncfg));
+    k.append(reinterpret_cast<const char *>(cfgs), sizeof(heget_config) * size_t(ncfg));
+    return k;
+}
+
+heget_result make_result(const double *st, int64_t n_gen)
+{
+    heget_result r{};
+    const double sum = st[0], sum2 = st[2];
+    r.sum_w = sum;
+    r.sum_w_comp = st[1];
+    r.sum_w2 = sum2;
+    r.n_gen = n_gen;
+    r.n_acc = static_cast<int64_t>(st[3]);
+    r.sigma_fb = n_gen > 0 ? sum / double(n_gen) : 0.0;
+    const double var = n_gen > 1 ? (sum2 / double(n_gen) - r.sigma_fb * r.sigma_fb) / double(n_gen - 1) : 0.0;
+    r.err_fb = std::sqrt(var > 0.0 ? var : 0.0);
+    return r;
 }
 
 }  // namespace
@@ -553,6 +801,200 @@ heget_status heget_xsec(int n, const heget_config *cfg, heget_result *out)
     return HEGET_OK;
 }
 
+heget_status heget_xsec_batch(const int *n, const heget_config *cfgs, int ncfg, heget_result *out)
+{
+    g_err.clear();
+    if (!n || !cfgs || !out) return fail(HEGET_ERR_ARG, "null pointer");
+    if (ncfg < 1 || ncfg > heget::kMaxSlices)
+        return fail(HEGET_ERR_RANGE, "ncfg must be in 1..8");
+    for (int i = 0; i < ncfg; ++i) {
+        HG_TRY(check_config(n[i], &cfgs[i]));
+        if (cfgs[i].prec != cfgs[0].prec)
+            return fail(HEGET_ERR_ARG, "all configurations of a batch need the same prec");
+    }
+    int64_t total = 0;
+    for (int i = 0; i < ncfg; ++i) total += cfgs[i].npoints;
+    if (total == 0) {
+        for (int i = 0; i < ncfg; ++i) out[i] = heget_result{};
+        return HEGET_OK;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    HG_TRY(ensure_device());
+    hipStream_t s = g.stream;
+    // sizes first, then the arena
+    SliceBufs sb[heget::kMaxSlices];
+    unsigned *flags;
+    unsigned long long *queue;
+    int64_t *item_start;
+    Arena sizing;
+    carve_batch(sizing, ncfg, n, cfgs, sb, &flags, &queue, &item_start);
+    void *base = nullptr;
+    HG_TRY(scratch(S_BATCH, sizing.off, &base));
+    Arena ar;
+    ar.base = static_cast<char *>(base);
+    carve_batch(ar, ncfg, n, cfgs, sb, &flags, &queue, &item_start);
+
+    const bool use_graph = std::getenv("HEGET_NO_GRAPH") == nullptr;
+    const std::string key = batch_key(ncfg, n, cfgs);
+    BatchGraph *bg = nullptr;
+    for (BatchGraph &b : g_graphs)
+        if (b.key == key) bg = &b;
+    HG_TRY(scratch_acquire(s));
+    if (!bg) {
+        if (g_graphs.size() >= 8) drop_graphs();
+        g_graphs.push_back(BatchGraph{});
+        bg = &g_graphs.back();
+        bg->key = key;
+        HG_HIP(hipHostMalloc(reinterpret_cast<void **>(&bg->staged),
+                             sizeof(double) * 4 * (heget::kMaxSlices + 1), hipHostMallocDefault));
+        if (use_graph) {
+            HG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            heget_status st = batch_enqueue(ncfg, n, cfgs, sb, flags, queue, item_start, bg->staged, s);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(s, &graph);
+            if (st < 0) return st;
+            HG_HIP(e);
+            e = hipGraphInstantiate(&bg->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HG_HIP(e);
+        }
+    }
+    if (bg->exec) {
+        HG_HIP(hipGraphLaunch(bg->exec, s));
+    } else {
+        HG_TRY(batch_enqueue(ncfg, n, cfgs, sb, flags, queue, item_start, bg->staged, s));
+    }
+    HG_TRY(scratch_release(s));
+    HG_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < ncfg; ++i) out[i] = make_result(bg->staged + 4 * i, cfgs[i].npoints);
+    unsigned fl = 0;
+    std::memcpy(&fl, bg->staged + 4 * heget::kMaxSlices, sizeof(unsigned));
+    if (fl & 1u) {
+        g_err = "some weights were not finite";
+        return HEGET_WARN_NONFINITE;
+    }
+    return HEGET_OK;
+}
+
+heget_status heget_autotune(int n, heget_prec prec, int64_t npoints, int *unrolled,
+                            int *helicities_per_walk, int *waves_per_block, double *ms)
+{
+    g_err.clear();
+    HG_TRY(check_n(n));
+    HG_TRY(check_prec(prec));
+    if (npoints < 64 || npoints > kMaxPoints)
+        return fail(HEGET_ERR_RANGE, "autotune needs 64 <= npoints < 2^31");
+    std::lock_guard<std::mutex> lk(g_mu);
+    HG_TRY(ensure_device());
+    hipStream_t s = g.stream;
+    double *d_mom, *d_w, *d_out;
+    unsigned *d_flags;
+    HG_TRY(scratch_t<double>(S_MOM, size_t(n + 2) * 4 * size_t(npoints), &d_mom));
+    HG_TRY(scratch_t<double>(S_WFAC, size_t(npoints), &d_w));
+    HG_TRY(scratch_t<unsigned>(S_FLAGS, 1, &d_flags));
+    // synthetic points: sqrt(shat) = 1 TeV, the paper's cuts applied to the
+    // weights only (every generated point is a valid input)
+    heget::GenParams gp{};
+    gp.mode = HEGET_FIXED_SHAT;
+    gp.seed = 0x5eed;
+    gp.npoints = npoints;
+    gp.sqrt_s = 1000.0;
+    gp.pt_min = 20.0;
+    gp.eta_max = 2.5;
+    gp.dr_min = 0.4;
+    gp.phase_volume_coef = phase_volume_coef(n);
+    gp.weight_kind = 0;
+    HG_TRY(scratch_acquire(s));
+    HG_HIP(heget::launch_gen(n, gp, d_mom, npoints, d_w, nullptr, nullptr, s));
+    HG_HIP(heget::launch_zero_u32(d_flags, 1, s));
+    hipEvent_t e0, e1;
+    HG_HIP(hipEventCreate(&e0));
+    HG_HIP(hipEventCreate(&e1));
+    int cnt = 0;
+    const heget::Me2Variant *all = heget::me2_variants(&cnt);
+    const heget::Me2Variant *best = nullptr;
+    double best_ms = 0.0;
+    for (int i = 0; i < cnt; ++i) {
+        const heget::Me2Variant &v = all[i];
+        if (v.prec != prec || v.n != n) continue;
+        const int nchunks = plan_chunks(v, npoints);
+        double *out = nullptr;
+        HG_TRY(scratch_t<double>(S_OUT, size_t(nchunks) * size_t(npoints), &out));
+        heget::Me2Args a{d_mom, npoints, nullptr, nullptr, npoints, nchunks,
+                         me2_coef(n, g_alpha, g_charge), out, npoints, d_flags};
+        HG_HIP(heget::launch_me2(v, a, s));  // warm-up
+        HG_HIP(hipEventRecord(e0, s));
+        const int reps = 3;
+        for (int r = 0; r < reps; ++r) HG_HIP(heget::launch_me2(v, a, s));
+        HG_HIP(hipEventRecord(e1, s));
+        HG_HIP(hipEventSynchronize(e1));
+        float t = 0.f;
+        HG_HIP(hipEventElapsedTime(&t, e0, e1));
+        const double per = double(t) / reps;
+        if (!best || per < best_ms) {
+            best = &v;
+            best_ms = per;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HG_TRY(scratch_release(s));
+    if (!best) return fail(HEGET_ERR_ARG, "no compiled amplitude kernel for this n/precision");
+    g_tuned[prec][n] = best;
+    save_tuning_cache(*best, best_ms, npoints);
+    if (unrolled) *unrolled = best->mb;
+    if (helicities_per_walk) *helicities_per_walk = best->h;
+    if (waves_per_block) *waves_per_block = best->wpb;
+    if (ms) *ms = best_ms;
+    return HEGET_OK;
+}
+
+heget_status heget_set_kernel_shape(int n, heget_prec prec, int mb, int h, int wpb)
+{
+    g_err.clear();
+    HG_TRY(check_n(n));
+    HG_TRY(check_prec(prec));
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (mb == 0 && h == 0 && wpb == 0) {
+        g_tuned[prec][n] = nullptr;
+        return HEGET_OK;
+    }
+    const heget::Me2Variant *v = find_variant(prec, n, mb, h, wpb);
+    if (!v) return fail(HEGET_ERR_ARG, "no compiled kernel shape with these parameters");
+    g_tuned[prec][n] = v;
+    return HEGET_OK;
+}
+
+heget_status heget_kernel_shapes(int n, heget_prec prec, int max, int *mb, int *h, int *wpb,
+                                 int *count)
+{
+    g_err.clear();
+    HG_TRY(check_n(n));
+    HG_TRY(check_prec(prec));
+    if (!count) return fail(HEGET_ERR_ARG, "null pointer");
+    int cnt = 0, k = 0;
+    const heget::Me2Variant *all = heget::me2_variants(&cnt);
+    const heget::Me2Variant *cur = pick_variant(prec, n);
+    // the shape in use first
+    if (cur && k < max && mb && h && wpb) {
+        mb[k] = cur->mb;
+        h[k] = cur->h;
+        wpb[k] = cur->wpb;
+    }
+    if (cur) ++k;
+    for (int i = 0; i < cnt; ++i) {
+        if (all[i].prec != prec || all[i].n != n || &all[i] == cur) continue;
+        if (k < max && mb && h && wpb) {
+            mb[k] = all[i].mb;
+            h[k] = all[i].h;
+            wpb[k] = all[i].wpb;
+        }
+        ++k;
+    }
+    *count = k;
+    return HEGET_OK;
+}
+
 heget_status heget_set_couplings(double alpha, double charge)
 {
     g_err.clear();
@@ -596,23 +1038,7 @@ heget_status heget_me2_flops(int n, heget_prec prec, double *flops_per_point, in
     if (!flops_per_point) return fail(HEGET_ERR_ARG, "null pointer");
     const heget::Me2Variant *v = pick_variant(prec, n);
     if (!v) return fail(HEGET_ERR_ARG, "no compiled amplitude kernel for this n/precision");
-    const double H = v->h;
-    const double passes = double(1 << n) / H;
-    const double nfact = factorial(n);
-    double nodes = 0.0;  // sum_{j=1}^{n-1} n!/(n-j)!
-    for (int j = 1; j <= n - 1; ++j) nodes += nfact / factorial(n - j);
-    double builds = n;   // vertex blocks built per walk
-    if (n > v->mb) {
-        double top = 0.0;
-        for (int j = 1; j <= n - v->mb; ++j) top += nfact / factorial(n - j);
-        builds = top + nfact / factorial(v->mb) * v->mb;
-    }
-    // node: q update 4, q^2 5, 1/q^2 1, scale 4 (=14) + per helicity 8 complex
-    // multiply-adds (=40); closing: 10 + 2 FP64 adds per helicity; vertex
-    // build 3 + 4 per helicity; |amp|^2 in FP64 4 per helicity
-    const double per_walk = nodes * (14.0 + 40.0 * H) + nfact * 12.0 * H + builds * (3.0 + 4.0 * H) +
-                            4.0 * H;
-    *flops_per_point = passes * per_walk;
+    *flops_per_point = me2_flops_per_point(n, v->mb, v->h);
     if (unrolled) *unrolled = v->mb;
     if (helicities_per_walk) *helicities_per_walk = v->h;
     return HEGET_OK;
@@ -632,6 +1058,7 @@ void heget_shutdown(void)
     for (hipEvent_t e : g.ev) (void)hipEventDestroy(e);
     g.ev.clear();
     g.ev_used = 0;
+    drop_graphs();
     if (g.pinned) (void)hipHostFree(g.pinned);
     g.pinned = nullptr;
     if (g.ws_free) (void)hipEventDestroy(g.ws_free);

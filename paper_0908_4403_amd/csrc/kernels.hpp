@@ -38,6 +38,36 @@ struct Me2Args {
 
 hipError_t launch_me2(const Me2Variant &v, const Me2Args &a, hipStream_t stream);
 
+// Mixed-n batch: one persistent launch whose waves take (slice, tile, chunk)
+// work items from an atomic queue, slices in the given order (most expensive
+// per item first).  Each slice runs the default shape for its n.
+constexpr int kMaxSlices = 8;
+struct SliceDesc {
+    const double *mom;
+    int64_t ld;
+    const int32_t *index;
+    const int64_t *d_count;
+    double *out;
+    int64_t ld_out;
+    double coef;
+    int n;
+    int nchunks;
+};
+struct BatchDesc {
+    SliceDesc s[kMaxSlices];
+    int nslices;
+    int64_t *item_start;           // [nslices + 1], written by launch_batch_plan
+    unsigned long long *queue;     // zeroed before the launch
+    unsigned *flags;
+};
+// item_start[s+1] = item_start[s] + ceil(count_s / 64) * nchunks_s (one thread).
+hipError_t launch_batch_plan(const BatchDesc &b, hipStream_t stream);
+// prec 0 = FP64, 1 = FP32; grid = number of persistent blocks of 256 threads.
+hipError_t launch_me2_batch(int prec, const BatchDesc &b, int grid, hipStream_t stream);
+int me2_batch_blocks_per_cu(int prec);
+// default (unrolled depth, helicities per walk) of the mixed kernel for n
+void me2_batch_shape(int prec, int n, int *mb, int *h);
+
 // Phase-space generation (FP64): momenta in SoA, weight (kind 0: Phi_n; kind
 // 1: full eq. (1)-(2) factor without |M|^2), accept flag, per-block accept
 // counts (blocks of 256 points).

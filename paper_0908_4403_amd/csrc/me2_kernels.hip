@@ -8,23 +8,16 @@
 
 namespace heget {
 
-template <typename R, int N, int MB, int H, int WPB>
-__global__ void __launch_bounds__(WPB * 64)
-me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict__ index,
-           const int64_t *__restrict__ d_count, int64_t count, int nchunks, double coef,
-           double *__restrict__ out, int64_t ld_out, unsigned *__restrict__ flags)
+// One work item: 64 points (one per lane) x one chunk of helicity walks.
+// `tab` is this wave's LDS photon table (kPhotonFields * N * 64 values of R).
+template <typename R, int N, int MB, int H>
+__device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t ld,
+                                         const int32_t *__restrict__ index, int64_t npts,
+                                         int64_t tile, int chunk, int nchunks, double coef,
+                                         double *__restrict__ out, int64_t ld_out,
+                                         unsigned *__restrict__ flags, R *tab, int lane)
 {
     constexpr bool kTopInLds = N > MB;
-    __shared__ R tab_all[kTopInLds ? WPB * kPhotonFields * N * 64 : 1];
-
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int64_t npts = d_count ? *d_count : count;
-    const int64_t ntiles = (npts + 63) >> 6;
-    const int64_t item = static_cast<int64_t>(blockIdx.x) * WPB + wave;
-    if (item >= ntiles * nchunks) return;  // whole wave
-    const int64_t tile = item / nchunks;
-    const int chunk = static_cast<int>(item - tile * nchunks);
     const int64_t i = tile * 64 + lane;
     const bool valid = i < npts;
     const int64_t ic = valid ? i : npts - 1;  // ragged tail: repeat the last point
@@ -44,7 +37,6 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
 
     PointIn<R, N> in;
     in.q0 = {static_cast<R>(-(E2 + p2z) * sc), static_cast<R>(-(E2 - p2z) * sc), R(0), R(0), R(0)};
-    R *tab = tab_all + (kTopInLds ? wave * kPhotonFields * N * 64 : 0);
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         const int r = 8 + 4 * j;
@@ -82,23 +74,164 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
 }
 
 template <typename R, int N, int MB, int H, int WPB>
+__global__ void __launch_bounds__(WPB * 64)
+me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict__ index,
+           const int64_t *__restrict__ d_count, int64_t count, int nchunks, double coef,
+           double *__restrict__ out, int64_t ld_out, unsigned *__restrict__ flags)
+{
+    __shared__ R tab_all[N > MB ? WPB * kPhotonFields * N * 64 : 1];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t npts = d_count ? *d_count : count;
+    const int64_t ntiles = (npts + 63) >> 6;
+    const int64_t item = static_cast<int64_t>(blockIdx.x) * WPB + wave;
+    if (item >= ntiles * nchunks) return;  // whole wave
+    const int64_t tile = item / nchunks;
+    const int chunk = static_cast<int>(item - tile * nchunks);
+    R *tab = tab_all + (N > MB ? wave * kPhotonFields * N * 64 : 0);
+    me2_item<R, N, MB, H>(mom, ld, index, npts, tile, chunk, nchunks, coef, out, ld_out, flags,
+                          tab, lane);
+}
+
+// ---------------------------------------------------------------- mixed-n batch
+
+// Shapes inside the mixed kernel: its register allocation is the largest of
+// its branches, so n = 4 takes the 3-level unroll there (the 4-level one alone
+// would halve the occupancy of every other n).
+template <typename R>
+struct BatchShape {
+    static constexpr int mb(int n) { return n < 4 ? n : (n == 4 ? 3 : 4); }
+    static constexpr int h = std::is_same<R, float>::value ? 2 : 1;
+};
+
+__device__ __forceinline__ int64_t wave_broadcast(int64_t v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(static_cast<int>(v & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane(static_cast<int>(v >> 32));
+    return (static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo);
+}
+
+__global__ void batch_plan_kernel(BatchDesc b)
+{
+    int64_t acc = 0;
+    b.item_start[0] = 0;
+    for (int s = 0; s < b.nslices; ++s) {
+        const int64_t cnt = *b.s[s].d_count;
+        acc += ((cnt + 63) / 64) * b.s[s].nchunks;
+        b.item_start[s + 1] = acc;
+    }
+}
+
+template <typename R, int N>
+__device__ __forceinline__ void batch_item(const SliceDesc &d, int64_t npts, int64_t tile, int chunk,
+                                           unsigned *flags, R *tab, int lane)
+{
+    me2_item<R, N, BatchShape<R>::mb(N), BatchShape<R>::h>(d.mom, d.ld, d.index, npts, tile, chunk,
+                                                           d.nchunks, d.coef, d.out, d.ld_out,
+                                                           flags, tab, lane);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) me2_batch_kernel(BatchDesc b)
+{
+    __shared__ R tab_all[4 * kPhotonFields * 8 * 64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    R *tab = tab_all + wave * kPhotonFields * 8 * 64;
+    const int64_t total = b.item_start[b.nslices];
+    for (;;) {
+        int64_t item = 0;
+        if (lane == 0) item = static_cast<int64_t>(atomicAdd(b.queue, 1ull));
+        item = wave_broadcast(item);
+        if (item >= total) break;
+        int s = 0;
+        while (s + 1 < b.nslices && item >= b.item_start[s + 1]) ++s;
+        const SliceDesc &d = b.s[s];
+        const int64_t local = item - b.item_start[s];
+        const int64_t tile = local / d.nchunks;
+        const int chunk = static_cast<int>(local - tile * d.nchunks);
+        const int64_t npts = *d.d_count;
+        switch (d.n) {
+        case 2: batch_item<R, 2>(d, npts, tile, chunk, b.flags, tab, lane); break;
+        case 3: batch_item<R, 3>(d, npts, tile, chunk, b.flags, tab, lane); break;
+        case 4: batch_item<R, 4>(d, npts, tile, chunk, b.flags, tab, lane); break;
+        case 5: batch_item<R, 5>(d, npts, tile, chunk, b.flags, tab, lane); break;
+        case 6: batch_item<R, 6>(d, npts, tile, chunk, b.flags, tab, lane); break;
+        case 7: batch_item<R, 7>(d, npts, tile, chunk, b.flags, tab, lane); break;
+        default: batch_item<R, 8>(d, npts, tile, chunk, b.flags, tab, lane); break;
+        }
+    }
+}
+
+hipError_t launch_batch_plan(const BatchDesc &b, hipStream_t stream)
+{
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(1), 0, stream, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_me2_batch(int prec, const BatchDesc &b, int grid, hipStream_t stream)
+{
+    if (prec == 1)
+        hipLaunchKernelGGL(me2_batch_kernel<float>, dim3(grid), dim3(256), 0, stream, b);
+    else
+        hipLaunchKernelGGL(me2_batch_kernel<double>, dim3(grid), dim3(256), 0, stream, b);
+    return hipGetLastError();
+}
+
+int me2_batch_blocks_per_cu(int prec)
+{
+    int blocks = 1;
+    const void *f = prec == 1 ? reinterpret_cast<const void *>(&me2_batch_kernel<float>)
+                              : reinterpret_cast<const void *>(&me2_batch_kernel<double>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, 256, 0) != hipSuccess || blocks < 1)
+        blocks = 1;
+    return blocks;
+}
+
+void me2_batch_shape(int prec, int n, int *mb, int *h)
+{
+    if (prec == 1) {
+        *mb = BatchShape<float>::mb(n);
+        *h = BatchShape<float>::h;
+    } else {
+        *mb = BatchShape<double>::mb(n);
+        *h = BatchShape<double>::h;
+    }
+}
+
+template <typename R, int N, int MB, int H, int WPB>
 constexpr Me2Variant variant()
 {
     return Me2Variant{std::is_same<R, float>::value ? 1 : 0, N, MB, H, WPB,
                       reinterpret_cast<const void *>(&me2_kernel<R, N, MB, H, WPB>)};
 }
 
-// Compiled shapes.  The first entry for each (prec, n) is the default.
+// Compiled shapes (the autotuner chooses among them per (prec, n)); the first
+// entry for each (prec, n) is the untuned default.  MB = unrolled depth, H =
+// helicities per walk, WPB = waves per block.
+#define HG_V(R, N, MB, H, WPB) variant<R, N, MB, H, WPB>()
 static const Me2Variant kVariants[] = {
     // FP32
-    variant<float, 2, 2, 2, 4>(), variant<float, 3, 3, 2, 4>(), variant<float, 4, 4, 2, 4>(),
-    variant<float, 5, 4, 2, 4>(), variant<float, 6, 4, 2, 4>(), variant<float, 7, 4, 2, 4>(),
-    variant<float, 8, 4, 2, 4>(),
+    HG_V(float, 2, 2, 2, 4), HG_V(float, 2, 2, 4, 4), HG_V(float, 2, 2, 1, 4), HG_V(float, 2, 2, 2, 1),
+    HG_V(float, 3, 3, 2, 4), HG_V(float, 3, 3, 4, 4), HG_V(float, 3, 3, 1, 4), HG_V(float, 3, 3, 2, 1),
+    HG_V(float, 4, 4, 2, 4), HG_V(float, 4, 3, 2, 4), HG_V(float, 4, 3, 4, 4), HG_V(float, 4, 4, 1, 4),
+    HG_V(float, 4, 4, 2, 1),
+    HG_V(float, 5, 4, 2, 4), HG_V(float, 5, 3, 2, 4), HG_V(float, 5, 3, 4, 4), HG_V(float, 5, 4, 1, 4),
+    HG_V(float, 5, 4, 2, 1),
+    HG_V(float, 6, 4, 2, 4), HG_V(float, 6, 3, 2, 4), HG_V(float, 6, 3, 4, 4), HG_V(float, 6, 4, 1, 4),
+    HG_V(float, 6, 4, 2, 1),
+    HG_V(float, 7, 4, 2, 4), HG_V(float, 7, 3, 2, 4), HG_V(float, 7, 3, 4, 4), HG_V(float, 7, 4, 1, 4),
+    HG_V(float, 8, 4, 2, 4), HG_V(float, 8, 3, 2, 4), HG_V(float, 8, 3, 4, 4), HG_V(float, 8, 4, 1, 4),
     // FP64
-    variant<double, 2, 2, 1, 4>(), variant<double, 3, 3, 1, 4>(), variant<double, 4, 4, 1, 4>(),
-    variant<double, 5, 4, 1, 4>(), variant<double, 6, 4, 1, 4>(), variant<double, 7, 4, 1, 4>(),
-    variant<double, 8, 4, 1, 4>(),
+    HG_V(double, 2, 2, 1, 4), HG_V(double, 2, 2, 2, 4), HG_V(double, 2, 2, 1, 1),
+    HG_V(double, 3, 3, 1, 4), HG_V(double, 3, 3, 2, 4), HG_V(double, 3, 3, 1, 1),
+    HG_V(double, 4, 4, 1, 4), HG_V(double, 4, 3, 1, 4), HG_V(double, 4, 3, 2, 4), HG_V(double, 4, 4, 1, 1),
+    HG_V(double, 5, 4, 1, 4), HG_V(double, 5, 3, 1, 4), HG_V(double, 5, 3, 2, 4), HG_V(double, 5, 4, 1, 1),
+    HG_V(double, 6, 4, 1, 4), HG_V(double, 6, 3, 1, 4), HG_V(double, 6, 3, 2, 4), HG_V(double, 6, 4, 1, 1),
+    HG_V(double, 7, 4, 1, 4), HG_V(double, 7, 3, 1, 4), HG_V(double, 7, 3, 2, 4), HG_V(double, 7, 4, 1, 1),
+    HG_V(double, 8, 4, 1, 4), HG_V(double, 8, 3, 1, 4), HG_V(double, 8, 3, 2, 4), HG_V(double, 8, 4, 1, 1),
 };
+#undef HG_V
 
 const Me2Variant *me2_variants(int *count)
 {

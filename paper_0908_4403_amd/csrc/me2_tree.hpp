@@ -219,6 +219,9 @@ template <typename R, int N, int MB, int H, int DEPTH>
 __device__ __forceinline__ void top_levels(const R *tab, int lane, uint32_t rem, uint32_t cfg0,
                                            const Chain<R, H> &c, const LMom<R> &q, Acc<H> &acc)
 {
+    // kept as a loop (not unrolled even where rem is a constant): the walk stays
+    // compact and register pressure stays that of one subtree
+#pragma nounroll
     for (uint32_t left = rem; left != 0u; left &= left - 1u) {
         const int j = __builtin_ctz(left);
         const LMom<R> k = lds_photon<R, N>(tab, j, lane);

@@ -1,0 +1,166 @@
+"""GPU parity where the oracle is too slow to run inside the test: stored
+oracle values (tests/golden/, written by tests/golden/make_golden.py, which
+calls only oracle/) and full-size workloads checked on sampled points.
+
+Bars: FP64 <= 1e-12 relative per point; FP32 median <= 1e-5, p99.9 <= 1e-3;
+sigma on the same sample <= 1e-10 (FP64) / 1e-5 (FP32); accept counts equal.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0908_4403_amd as H
+    return H
+
+
+def read_me2(fname):
+    meta, rows = {}, []
+    for line in open(os.path.join(GOLDEN, fname)):
+        if line.startswith("# n="):
+            meta = dict(kv.split("=") for kv in line[2:].split())
+        elif line.strip() and not line.startswith("#"):
+            i, v = line.split()
+            rows.append((int(i), float(v)))
+    return int(meta["n"]), float(meta["sqrt_shat"]), int(meta["seed"]), rows
+
+
+def read_xsec(fname):
+    d = {}
+    for line in open(os.path.join(GOLDEN, fname)):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            d[k] = float(v) if any(c in v for c in ".e") else int(v)
+    return d
+
+
+def h_config(H, g, prec):
+    return H.Config(mode=int(g["mode"]), prec=prec, seed=int(g["seed"]), npoints=int(g["npoints"]),
+                    sqrt_s=float(g["sqrt_s"]), sqrt_shat_lo=float(g["sqrt_shat_lo"]),
+                    sqrt_shat_hi=float(g["sqrt_shat_hi"]), pt_min=float(g["pt_min"]),
+                    eta_max=float(g["eta_max"]), dr_min=float(g["dr_min"]))
+
+
+@pytest.mark.parametrize("fname", ["me2_n7_1500GeV_seed7.txt", "me2_n8_2TeV_seed4_orderings.txt",
+                                   "me2_n8_2TeV_seed4_subsets.txt"])
+def test_me2_large_n_against_stored_oracle(H, orc, fname):
+    n, sqrt_s, seed, rows = read_me2(fname)
+    ev = np.array([orc.cm_event(n, sqrt_s, seed, i) for i, _ in rows])
+    ref = np.array([v for _, v in rows])
+    got64 = H.me2(ev, H.FP64)
+    rel64 = np.abs(got64 / ref - 1)
+    got32 = H.me2(ev, H.FP32)
+    rel32 = np.abs(got32 / ref - 1)
+    print(f"{fname}: FP64 max {rel64.max():.2e}; FP32 median {np.median(rel32):.2e} "
+          f"p99.9 {np.quantile(rel32, 0.999):.2e} max {rel32.max():.2e}", flush=True)
+    assert rel64.max() <= 1e-12
+    assert np.median(rel32) <= 1e-5 and np.quantile(rel32, 0.999) <= 1e-3
+
+
+@pytest.mark.parametrize("fname", ["xsec_uubar_4a_1TeV_2p20.txt", "xsec_pp_5a_14TeV_first2p16.txt",
+                                   "xsec_uubar_8a_2TeV_first2p12.txt"])
+def test_xsec_against_stored_oracle(H, fname):
+    g = read_xsec(fname)
+    for prec, tol in (("FP64", 1e-10), ("FP32", 1e-5)):
+        got = H.xsec(int(g["n"]), h_config(H, g, getattr(H, prec)))
+        print(fname, prec, got["sigma_fb"], g["sigma_fb"], flush=True)
+        assert got["n_gen"] == g["n_gen"] and got["n_acc"] == g["n_acc"]
+        assert abs(got["sigma_fb"] / g["sigma_fb"] - 1) < tol
+        assert abs(got["err_fb"] / g["err_fb"] - 1) < 1e-4
+
+
+def test_mixed_batch_against_stored_oracle(H):
+    gs = [read_xsec(f) for f in sorted(os.listdir(GOLDEN)) if f.startswith("xsec_mixed_n")]
+    assert len(gs) == 6
+    ns = [int(g["n"]) for g in gs]
+    for prec, tol in (("FP64", 1e-10), ("FP32", 1e-5)):
+        res = H.xsec_batch(ns, [h_config(H, g, getattr(H, prec)) for g in gs])
+        again = H.xsec_batch(ns, [h_config(H, g, getattr(H, prec)) for g in gs])  # graph replay
+        assert res == again
+        for g, r in zip(gs, res):
+            assert r["n_acc"] == g["n_acc"], (g["n"], r)
+            assert abs(r["sigma_fb"] / g["sigma_fb"] - 1) < tol, (g["n"], prec, r["sigma_fb"], g["sigma_fb"])
+
+
+def _full_size_sampled(H, orc, wl, prec, nsample, subsets):
+    """Full-size |M|^2 on the device; oracle on a random sample of survivors."""
+    import torch
+    n, N = wl["n"], wl["npoints"]
+    mom = torch.empty(((n + 2) * 4, N), dtype=torch.float64, device="cuda")
+    w = torch.empty(N, dtype=torch.float64, device="cuda")
+    H.gen_points_device(n, wl["sqrt_s"], mom, w, wl["cuts"], wl["seed"])
+    out = torch.empty(N, dtype=torch.float64, device="cuda")
+    H.me2_device(n, mom, out, prec)
+    torch.cuda.synchronize()
+    acc = torch.nonzero(w > 0).flatten().cpu().numpy()
+    rng = np.random.default_rng(0)
+    pick = np.sort(rng.choice(acc, size=min(nsample, acc.size), replace=False))
+    ev = np.array([orc.cm_event(n, wl["sqrt_s"], wl["seed"], int(i)) for i in pick])
+    ref = (orc.me2_subsets_batch(ev) if subsets else orc.me2_batch(ev))[0]
+    got = out.cpu().numpy()[pick]
+    return np.abs(got / ref - 1), acc.size
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+def test_full_size_4a_sampled(H, orc, prec):
+    from paper_0908_4403_amd.workloads import WORKLOADS
+    rel, nacc = _full_size_sampled(H, orc, WORKLOADS["uubar_4a_1TeV_2p20"], getattr(H, prec), 2000, False)
+    print(prec, "n=4 full size", nacc, "survivors; sampled max rel", rel.max(), flush=True)
+    if prec == "FP64":
+        assert rel.max() <= 1e-12
+    else:
+        assert np.median(rel) <= 1e-5 and np.quantile(rel, 0.999) <= 1e-3
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+def test_full_size_8a_sampled(H, orc, prec):
+    from paper_0908_4403_amd.workloads import WORKLOADS
+    rel, nacc = _full_size_sampled(H, orc, WORKLOADS["uubar_8a_2TeV_2p18"], getattr(H, prec), 256, True)
+    print(prec, "n=8 full size", nacc, "survivors; sampled max rel", rel.max(), flush=True)
+    if prec == "FP64":
+        assert rel.max() <= 1e-12
+    else:
+        assert np.median(rel) <= 1e-5 and np.quantile(rel, 0.999) <= 1e-3
+
+
+def test_full_size_pp_5a_properties(H):
+    """pp -> 5 photons, 2^22 points: deterministic, FP32 within 1e-5 of FP64,
+    batch form equal to the single form."""
+    from paper_0908_4403_amd.workloads import WORKLOADS
+    wl = WORKLOADS["pp_5a_14TeV_2p22"]
+    kw = dict(mode=wl["mode"], seed=wl["seed"], npoints=wl["npoints"], sqrt_s=wl["sqrt_s"],
+              sqrt_shat_lo=wl["lo"], pt_min=wl["cuts"][0], eta_max=wl["cuts"][1], dr_min=wl["cuts"][2])
+    a64 = H.xsec(5, H.Config(prec=H.FP64, **kw))
+    a32 = H.xsec(5, H.Config(prec=H.FP32, **kw))
+    b32 = H.xsec(5, H.Config(prec=H.FP32, **kw))
+    (c32,) = H.xsec_batch([5], [H.Config(prec=H.FP32, **kw)])
+    print("pp 5a full:", a64["sigma_fb"], "+-", a64["err_fb"], "fb;", a64["n_acc"], "accepted", flush=True)
+    assert a32 == b32
+    assert a32["n_acc"] == a64["n_acc"] == c32["n_acc"]
+    assert abs(a32["sigma_fb"] / a64["sigma_fb"] - 1) < 1e-5
+    assert abs(c32["sigma_fb"] / a32["sigma_fb"] - 1) < 1e-12
+
+
+def test_full_size_mixed_batch_vs_single(H):
+    """The mixed n = 2..7 workload in one batch equals one call per n."""
+    from paper_0908_4403_amd.workloads import MIXED_BATCH
+    cfgs = [H.Config(mode=s["mode"], prec=H.FP32, seed=s["seed"], npoints=s["npoints"],
+                     sqrt_shat_lo=s["lo"], sqrt_shat_hi=s["hi"], pt_min=s["cuts"][0],
+                     eta_max=s["cuts"][1], dr_min=s["cuts"][2]) for s in MIXED_BATCH]
+    ns = [s["n"] for s in MIXED_BATCH]
+    batch = H.xsec_batch(ns, cfgs)
+    for n, c, b in zip(ns, cfgs, batch):
+        single = H.xsec(n, c)
+        assert single["n_acc"] == b["n_acc"]
+        assert abs(single["sigma_fb"] / b["sigma_fb"] - 1) < 1e-12, (n, single, b)

@@ -115,3 +115,37 @@ def test_me2_device_matches_host(H, orc):
         torch.cuda.synchronize()
         host = H.me2(ev, prec)
         assert np.array_equal(out.cpu().numpy(), host)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 7, 8])
+def test_every_compiled_shape_matches_oracle(H, orc, n):
+    """Each unrolled depth / helicities-per-walk / waves-per-block shape the
+    autotuner may pick gives the oracle's |M|^2 (FP64 shapes to 1e-12)."""
+    count = {2: 200, 3: 130, 4: 70, 5: 67, 6: 20, 7: 3, 8: 1}[n]
+    ev = cut_events(orc, n, 1200.0, 300 + n, count)
+    ref = (orc.me2_subsets_batch(ev) if n >= 7 else orc.me2_batch(ev))[0]
+    try:
+        for prec in (H.FP64, H.FP32):
+            for shape in H.kernel_shapes(n, prec):
+                H.set_kernel_shape(n, prec, shape)
+                rel = np.abs(H.me2(ev, prec) / ref - 1)
+                bound = 1e-12 if prec == H.FP64 else 1e-3
+                assert rel.max() <= bound, (n, prec, shape, rel.max())
+    finally:
+        H.set_kernel_shape(n, H.FP64)
+        H.set_kernel_shape(n, H.FP32)
+
+
+def test_autotune_picks_a_compiled_shape(H, orc, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("HEGET_TUNING_CACHE", str(cache))
+    r = H.autotune(5, H.FP32, 16384)
+    shape = (r["unrolled"], r["helicities_per_walk"], r["waves_per_block"])
+    assert shape == H.kernel_shapes(5, H.FP32)[0]
+    assert r["ms"] > 0
+    line = cache.read_text().strip()
+    assert f'"n": 5, "mb": {shape[0]}, "h": {shape[1]}, "wpb": {shape[2]}' in line
+    ev = cut_events(orc, 5, 1000.0, 17, 100)
+    ref, _ = orc.me2_batch(ev)
+    assert np.median(np.abs(H.me2(ev, H.FP32) / ref - 1)) <= 1e-5
+    H.set_kernel_shape(5, H.FP32)
