@@ -135,18 +135,38 @@ heget_status heget_xsec(int n, const heget_config *cfg, heget_result *out);
 heget_status heget_xsec_async(int n, const heget_config *cfg, heget_result *out,
                               heget_stream stream);
 
+/* heget_xsec enqueued on `stream` with the result record written by the
+ * device into d_out, which must be device memory or host memory the device
+ * can write (e.g. from hipHostMalloc); no host callback or synchronisation is
+ * involved, so calls can be chained and captured.  npoints must be > 0.
+ * Non-finite weights are not reported in the status (check d_out->sigma_fb). */
+heget_status heget_xsec_device(int n, const heget_config *cfg, heget_result *d_out,
+                               heget_stream stream);
+
 /* Several cross sections in one device pass (e.g. n = 2..7 with different
- * point counts): generation, cuts and compaction per configuration, then ONE
- * persistent amplitude launch whose waves pull (configuration, 64-point tile,
- * helicity chunk) work items from an atomic queue, most expensive items
- * first, then the per-configuration reductions.  The whole sequence is
- * captured in a hipGraph on first use and replayed for the same arguments.
+ * point counts), captured on first use as ONE hipGraph that later calls with
+ * the same arguments replay.  Two schedules of the amplitude work:
+ *   1 persistent: one persistent amplitude launch whose waves pull
+ *     (configuration, 64-point tile, helicity chunk) work items from an
+ *     atomic queue, most expensive items first;
+ *   2 branches: one graph branch per configuration (generation, compaction,
+ *     the tuned amplitude kernel for its n, reduction), branches running
+ *     concurrently so memory-bound and compute-bound work overlap.
+ * With schedule 0 (auto, the default) the first call captures both, times
+ * one launch of each and keeps the faster for these arguments.
  * n[ncfg], cfgs[ncfg] (in, host), out[ncfg] (out, host); 1 <= ncfg <= 8, all
  * with the same prec.  Results equal heget_xsec per configuration up to the
- * rounding of the helicity-chunk grouping.  Set HEGET_NO_GRAPH=1 in the
- * environment to launch without graph capture. */
+ * rounding of the kernel shape used (FP32: within 1e-5). */
 heget_status heget_xsec_batch(const int *n, const heget_config *cfgs, int ncfg,
                               heget_result *out);
+
+/* Schedule of later heget_xsec_batch calls: 0 auto, 1 persistent, 2 branches.
+ * Drops captured batches. */
+heget_status heget_set_batch_schedule(int schedule);
+
+/* Schedule a batch with these arguments runs (0 if it has not run yet). */
+heget_status heget_batch_schedule_in_use(const int *n, const heget_config *cfgs, int ncfg,
+                                         int *schedule);
 
 /* Couplings used by heget_me2 / heget_me2_device (defaults: 1/137, 2/3). */
 heget_status heget_set_couplings(double alpha, double charge);
@@ -158,36 +178,48 @@ heget_status heget_set_couplings(double alpha, double charge);
 heget_status heget_timing_enable(int on);
 heget_status heget_timing_read(double *me2_ms, int64_t *me2_launches, int reset);
 
+/* Shape of the amplitude kernel (the autotuner's search space).
+ *   unrolled             photons left in a subtree that is unrolled at compile
+ *                        time with its photons in registers (2..5); when it
+ *                        covers all n photons the helicity configurations of
+ *                        one walk also share every current that does not yet
+ *                        depend on the photons where they differ
+ *   helicities_per_walk  helicity configurations sharing one walk of the tree
+ *   closing              1: every ordering closes photon by photon (iovxx0 at
+ *                        the leaves); 2: the last two photons close together
+ *                        through pair vectors built from the u end (the current
+ *                        reuse of the paper's MadGraph program, Appendix A.1)
+ *   waves_per_block      64-lane waves per workgroup */
+typedef struct {
+    int32_t unrolled, helicities_per_walk, closing, waves_per_block;
+} heget_shape;
+
 /* Algorithmic floating-point operations per point of the amplitude kernel
  * that heget_me2 / heget_xsec run for (n, prec): FMA = 2, add/mul/reciprocal
  * = 1, counted on the schedule actually executed (the 2^n helicities of one
- * quark-helicity block, shared-prefix tree of the n! orderings, H helicities
- * per tree walk).  Per-point O(n) set-up is not counted.  Also returns the
- * unrolled depth and the helicities per walk of that kernel (may be NULL). */
-heget_status heget_me2_flops(int n, heget_prec prec, double *flops_per_point, int *unrolled,
-                             int *helicities_per_walk);
+ * quark-helicity block; the shape's tree, closing and helicity sharing).
+ * Per-point O(n) set-up is not counted.  *shape (may be NULL) receives the
+ * shape in use. */
+heget_status heget_me2_flops(int n, heget_prec prec, double *flops_per_point, heget_shape *shape);
 
 /* Autotuner.  Times every compiled shape of the amplitude kernel for (n,
- * prec) -- unrolled depth of the ordering tree, helicities per tree walk,
- * waves per workgroup -- on npoints synthetic points (sqrt(shat) = 1 TeV)
- * generated on the device, and makes the fastest the shape every later call
- * uses for (n, prec) in this process.  If HEGET_TUNING_CACHE names a file,
- * the choice is also written there (one JSON object per line) and read back
- * by later processes on first device use.  Outputs (host, may be NULL): the
- * chosen shape and its time per launch in ms.  64 <= npoints < 2^31. */
-heget_status heget_autotune(int n, heget_prec prec, int64_t npoints, int *unrolled,
-                            int *helicities_per_walk, int *waves_per_block, double *ms);
+ * prec) on npoints synthetic points (sqrt(shat) = 1 TeV) generated on the
+ * device, and makes the fastest the shape every later call uses for (n,
+ * prec) in this process.  If HEGET_TUNING_CACHE names a file, the choice is
+ * also written there (one JSON object per line) and read back by later
+ * processes on first device use.  *chosen and *ms (may be NULL) receive the
+ * chosen shape and its time per launch.  64 <= npoints < 2^31. */
+heget_status heget_autotune(int n, heget_prec prec, int64_t npoints, heget_shape *chosen,
+                            double *ms);
 
-/* The compiled shapes for (n, prec), the one in use first: mb[i] (unrolled
- * depth), h[i] (helicities per walk), wpb[i] (waves per block) for i < max
- * (arrays may be NULL when max = 0); *count receives the number of shapes. */
-heget_status heget_kernel_shapes(int n, heget_prec prec, int max, int *mb, int *h, int *wpb,
-                                 int *count);
+/* The compiled shapes for (n, prec), the one in use first, into shapes[i]
+ * for i < max (shapes may be NULL when max = 0); *count receives how many
+ * exist. */
+heget_status heget_kernel_shapes(int n, heget_prec prec, int max, heget_shape *shapes, int *count);
 
-/* Use the compiled shape (mb, h, wpb) for (n, prec) from now on in this
- * process; (0, 0, 0) restores the default.  HEGET_ERR_ARG if no such shape
- * was compiled (heget_kernel_shapes lists them). */
-heget_status heget_set_kernel_shape(int n, heget_prec prec, int mb, int h, int wpb);
+/* Use a compiled shape for (n, prec) from now on in this process; NULL
+ * restores the default.  HEGET_ERR_ARG if no such shape was compiled. */
+heget_status heget_set_kernel_shape(int n, heget_prec prec, const heget_shape *shape);
 
 /* Message of the last failure on this thread ("" if none). */
 const char *heget_last_error(void);

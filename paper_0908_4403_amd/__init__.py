@@ -32,7 +32,9 @@ FP64, FP32 = 0, 1
 FIXED_SHAT, UNIFORM_SQRTSHAT, PP_TOY = 0, 1, 2
 
 EXPORTS = ["heget_gen_points", "heget_gen_points_device", "heget_me2", "heget_me2_device",
-           "heget_xsec", "heget_xsec_async", "heget_xsec_batch", "heget_set_couplings",
+           "heget_xsec", "heget_xsec_async", "heget_xsec_device", "heget_xsec_batch",
+           "heget_set_batch_schedule", "heget_batch_schedule_in_use",
+           "heget_set_couplings",
            "heget_timing_enable",
            "heget_timing_read", "heget_me2_flops", "heget_autotune", "heget_kernel_shapes",
            "heget_set_kernel_shape",
@@ -48,6 +50,14 @@ class _Config(C.Structure):
                 ("npoints", C.c_int64), ("sqrt_s", C.c_double), ("sqrt_shat_lo", C.c_double),
                 ("sqrt_shat_hi", C.c_double), ("cuts", Cuts), ("alpha", C.c_double),
                 ("charge", C.c_double)]
+
+
+class Shape(C.Structure):
+    _fields_ = [("unrolled", C.c_int32), ("helicities_per_walk", C.c_int32),
+                ("closing", C.c_int32), ("waves_per_block", C.c_int32)]
+
+    def as_tuple(self):
+        return (self.unrolled, self.helicities_per_walk, self.closing, self.waves_per_block)
 
 
 class Result(C.Structure):
@@ -68,15 +78,18 @@ _lib.heget_me2.argtypes = [C.c_int, C.c_int64, _dp, _dp, C.c_int]
 _lib.heget_me2_device.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
 _lib.heget_xsec.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result)]
 _lib.heget_xsec_async.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result), C.c_void_p]
+_lib.heget_set_batch_schedule.argtypes = [C.c_int]
+_lib.heget_batch_schedule_in_use.argtypes = [C.POINTER(C.c_int), C.POINTER(_Config), C.c_int,
+                                             C.POINTER(C.c_int)]
+_lib.heget_xsec_device.argtypes = [C.c_int, C.POINTER(_Config), C.c_void_p, C.c_void_p]
 _lib.heget_xsec_batch.argtypes = [C.POINTER(C.c_int), C.POINTER(_Config), C.c_int, C.POINTER(Result)]
 _lib.heget_set_couplings.argtypes = [C.c_double, C.c_double]
 _lib.heget_timing_enable.argtypes = [C.c_int]
 _lib.heget_timing_read.argtypes = [_dp, C.POINTER(C.c_int64), C.c_int]
-_lib.heget_me2_flops.argtypes = [C.c_int, C.c_int, _dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
-_ipt = C.POINTER(C.c_int)
-_lib.heget_autotune.argtypes = [C.c_int, C.c_int, C.c_int64, _ipt, _ipt, _ipt, _dp]
-_lib.heget_kernel_shapes.argtypes = [C.c_int, C.c_int, C.c_int, _ipt, _ipt, _ipt, _ipt]
-_lib.heget_set_kernel_shape.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+_lib.heget_me2_flops.argtypes = [C.c_int, C.c_int, _dp, C.POINTER(Shape)]
+_lib.heget_autotune.argtypes = [C.c_int, C.c_int, C.c_int64, C.POINTER(Shape), _dp]
+_lib.heget_kernel_shapes.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(Shape), C.POINTER(C.c_int)]
+_lib.heget_set_kernel_shape.argtypes = [C.c_int, C.c_int, C.POINTER(Shape)]
 _lib.heget_last_error.restype = C.c_char_p
 _lib.heget_shutdown.restype = None
 for _f in EXPORTS[:-2]:
@@ -190,6 +203,37 @@ def xsec_batch(ns, cfgs, return_status: bool = False):
     return (out, st) if return_status else out
 
 
+def xsec_device(n: int, cfg: Config, out, stream=None) -> None:
+    """Enqueue the cross section with its result record written by the device into
+    `out`: a torch uint8/int64 tensor of >= 56 bytes on the GPU or in pinned host
+    memory (layout of Result; read it back with result_from_bytes)."""
+    c = cfg.c()
+    _check(_lib.heget_xsec_device(n, C.byref(c), C.c_void_p(out.data_ptr()), _stream(stream)),
+           "heget_xsec_device")
+
+
+def result_from_bytes(buf) -> dict:
+    """Decode a Result record (56 bytes, e.g. from xsec_device) into a dict."""
+    raw = bytes(buf[:C.sizeof(Result)])
+    return Result.from_buffer_copy(raw).as_dict()
+
+
+BATCH_AUTO, BATCH_PERSISTENT, BATCH_BRANCHES = 0, 1, 2
+
+
+def set_batch_schedule(schedule: int) -> None:
+    _check(_lib.heget_set_batch_schedule(schedule), "heget_set_batch_schedule")
+
+
+def batch_schedule_in_use(ns, cfgs) -> int:
+    k = len(ns)
+    na = (C.c_int * k)(*ns)
+    ca = (_Config * k)(*[c.c() for c in cfgs])
+    s = C.c_int()
+    _check(_lib.heget_batch_schedule_in_use(na, ca, k, C.byref(s)), "heget_batch_schedule_in_use")
+    return s.value
+
+
 class XsecAsync:
     """Handle of an enqueued heget_xsec_async; .result() after the stream completes.
 
@@ -252,36 +296,42 @@ def timing_read(reset: bool = True):
     return ms.value, cnt.value
 
 
+SHAPE_FIELDS = ("unrolled", "helicities_per_walk", "closing", "waves_per_block")
+
+
 def me2_flops(n: int, prec: int = FP32):
-    """(algorithmic flops per point, unrolled depth, helicities per walk) of the kernel run."""
-    f, mb, h = C.c_double(), C.c_int(), C.c_int()
-    _check(_lib.heget_me2_flops(n, prec, C.byref(f), C.byref(mb), C.byref(h)), "heget_me2_flops")
-    return f.value, mb.value, h.value
+    """(algorithmic flops per point, shape tuple) of the kernel in use for (n, prec)."""
+    f, s = C.c_double(), Shape()
+    _check(_lib.heget_me2_flops(n, prec, C.byref(f), C.byref(s)), "heget_me2_flops")
+    return f.value, s.as_tuple()
 
 
 def autotune(n: int, prec: int = FP32, npoints: int = 1 << 18) -> dict:
     """Time every compiled kernel shape for (n, prec) and keep the fastest."""
-    mb, h, wpb, ms = C.c_int(), C.c_int(), C.c_int(), C.c_double()
-    _check(_lib.heget_autotune(n, prec, npoints, C.byref(mb), C.byref(h), C.byref(wpb), C.byref(ms)),
-           "heget_autotune")
-    return {"unrolled": mb.value, "helicities_per_walk": h.value, "waves_per_block": wpb.value,
-            "ms": ms.value}
+    s, ms = Shape(), C.c_double()
+    _check(_lib.heget_autotune(n, prec, npoints, C.byref(s), C.byref(ms)), "heget_autotune")
+    d = dict(zip(SHAPE_FIELDS, s.as_tuple()))
+    d["ms"] = ms.value
+    return d
 
 
 def kernel_shapes(n: int, prec: int = FP32):
-    """[(unrolled depth, helicities per walk, waves per block)], the shape in use first."""
+    """Compiled shapes for (n, prec) as tuples (unrolled, helicities_per_walk,
+    closing, waves_per_block), the shape in use first."""
     cnt = C.c_int()
-    _check(_lib.heget_kernel_shapes(n, prec, 0, None, None, None, C.byref(cnt)), "heget_kernel_shapes")
-    k = cnt.value
-    mb, h, wpb = (C.c_int * k)(), (C.c_int * k)(), (C.c_int * k)()
-    _check(_lib.heget_kernel_shapes(n, prec, k, mb, h, wpb, C.byref(cnt)), "heget_kernel_shapes")
-    return list(zip(mb, h, wpb))
+    _check(_lib.heget_kernel_shapes(n, prec, 0, None, C.byref(cnt)), "heget_kernel_shapes")
+    arr = (Shape * cnt.value)()
+    _check(_lib.heget_kernel_shapes(n, prec, cnt.value, arr, C.byref(cnt)), "heget_kernel_shapes")
+    return [s.as_tuple() for s in arr]
 
 
 def set_kernel_shape(n: int, prec: int, shape=None) -> None:
-    """Force a compiled shape (unrolled, helicities_per_walk, waves_per_block); None = default."""
-    mb, h, wpb = shape if shape is not None else (0, 0, 0)
-    _check(_lib.heget_set_kernel_shape(n, prec, mb, h, wpb), "heget_set_kernel_shape")
+    """Force a compiled shape (tuple as from kernel_shapes); None = default."""
+    if shape is None:
+        _check(_lib.heget_set_kernel_shape(n, prec, None), "heget_set_kernel_shape")
+    else:
+        s = Shape(*shape)
+        _check(_lib.heget_set_kernel_shape(n, prec, C.byref(s)), "heget_set_kernel_shape")
 
 
 def shutdown() -> None:

@@ -20,7 +20,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libheget.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["me2_kernels.hip", "mc_kernels.hip", "heget_api.cpp"]
+SOURCES = ["me2_shapes_f32_lo.hip", "me2_shapes_f32_mid.hip", "me2_shapes_f32_hi.hip",
+           "me2_shapes_f64_lo.hip", "me2_shapes_f64_mid.hip", "me2_shapes_f64_hi.hip",
+           "me2_batch.hip", "me2_registry.cpp", "mc_kernels.hip", "heget_api.cpp"]
 ARCH = os.environ.get("HEGET_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -47,7 +49,7 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -59,6 +59,10 @@ struct State {
     std::vector<size_t> cap;
     double *pinned = nullptr;         // staging ring for results (kRing slots of 8 doubles)
     std::atomic<unsigned> ring{0};
+    // side streams and fork/join events of the parallel batch schedule
+    hipStream_t side[8] = {};
+    hipEvent_t fork = nullptr, join[8] = {};
+    int batch_schedule = 0;  // 0 auto, 1 persistent kernel, 2 parallel branches
     // timing of the amplitude kernel
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -77,8 +81,10 @@ enum Slot {
 // Captured mixed-n batches, keyed by their configuration; replayed on repeat calls.
 struct BatchGraph {
     std::string key;
-    hipGraphExec_t exec = nullptr;
-    double *staged = nullptr;  // pinned: 4 doubles per slice + flags
+    hipGraphExec_t exec = nullptr;  // the schedule in use for this key
+    hipGraphExec_t other = nullptr; // kept only while "auto" compares the two
+    double *staged = nullptr;       // pinned: 4 doubles per slice + flags
+    int schedule = 0;               // 1 persistent, 2 branches
 };
 std::vector<BatchGraph> g_graphs;
 
@@ -86,6 +92,7 @@ void drop_graphs()
 {
     for (BatchGraph &b : g_graphs) {
         if (b.exec) (void)hipGraphExecDestroy(b.exec);
+        if (b.other) (void)hipGraphExecDestroy(b.other);
         if (b.staged) (void)hipHostFree(b.staged);
     }
     g_graphs.clear();
@@ -223,15 +230,15 @@ double me2_coef(int n, double alpha, double charge)
     return 2.0 * std::pow(e2q2, n);
 }
 
-double me2_flops_per_point(int n, int mb, int h);
+double me2_flops_per_point(int n, int mb, int h, int cl);
 
 // Helicity chunks per work item: enough wave-sized items for small batches
 // (>= 8192), and no item above ~2e8 flops so the tail of a launch stays short.
-int plan_chunks_shape(int n, int mb, int h, int64_t points_expected)
+int plan_chunks_shape(int n, int mb, int h, int cl, int64_t points_expected)
 {
     const int passes = (1 << n) / h;
     const int64_t tiles = (points_expected + 63) / 64;
-    const double item_flops = 64.0 * me2_flops_per_point(n, mb, h);
+    const double item_flops = 64.0 * me2_flops_per_point(n, mb, h, cl);
     int c = 1;
     while (c < passes && (tiles * c < 8192 || item_flops / c > 2e8)) c *= 2;
     return c;
@@ -239,7 +246,7 @@ int plan_chunks_shape(int n, int mb, int h, int64_t points_expected)
 
 int plan_chunks(const heget::Me2Variant &v, int64_t points_expected)
 {
-    return plan_chunks_shape(v.n, v.mb, v.h, points_expected);
+    return plan_chunks_shape(v.n, v.mb, v.h, v.cl, points_expected);
 }
 
 // Shape chosen by the autotuner (or loaded from the tuning cache) per (prec, n).
@@ -251,14 +258,20 @@ const heget::Me2Variant *pick_variant(int prec, int n)
     return heget::me2_default(prec, n);
 }
 
-const heget::Me2Variant *find_variant(int prec, int n, int mb, int h, int wpb)
+const heget::Me2Variant *find_variant(int prec, int n, int mb, int h, int cl, int wpb)
 {
     int cnt = 0;
     const heget::Me2Variant *v = heget::me2_variants(&cnt);
     for (int i = 0; i < cnt; ++i)
-        if (v[i].prec == prec && v[i].n == n && v[i].mb == mb && v[i].h == h && v[i].wpb == wpb)
+        if (v[i].prec == prec && v[i].n == n && v[i].mb == mb && v[i].h == h && v[i].cl == cl &&
+            v[i].wpb == wpb)
             return &v[i];
     return nullptr;
+}
+
+heget_shape shape_of(const heget::Me2Variant &v)
+{
+    return heget_shape{v.mb, v.h, v.cl, v.wpb};
 }
 
 // Tuning cache: one JSON object per line,
@@ -272,11 +285,11 @@ void load_tuning_cache()
     char line[512];
     while (std::fgets(line, sizeof line, f)) {
         char arch[64] = {0};
-        int prec, n, mb, h, wpb;
-        if (std::sscanf(line, " {\"arch\": \"%63[^\"]\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"wpb\": %d",
-                        arch, &prec, &n, &mb, &h, &wpb) == 6 &&
-            g_arch == arch) {
-            const heget::Me2Variant *v = find_variant(prec, n, mb, h, wpb);
+        int prec, n, mb, h, cl, wpb;
+        if (std::sscanf(line, " {\"arch\": \"%63[^\"]\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d",
+                        arch, &prec, &n, &mb, &h, &cl, &wpb) == 7 &&
+            g_arch == arch && prec >= 0 && prec < 2 && n >= 2 && n <= 8) {
+            const heget::Me2Variant *v = find_variant(prec, n, mb, h, cl, wpb);
             if (v) g_tuned[prec][n] = v;
         }
     }
@@ -299,35 +312,104 @@ void save_tuning_cache(const heget::Me2Variant &v, double ms, int64_t points)
     }
     if (FILE *f = std::fopen(path, "w")) {
         for (const std::string &l : keep) std::fputs(l.c_str(), f);
-        std::fprintf(f, "{\"arch\": \"%s\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"wpb\": %d, \"ms\": %.6f, \"points\": %lld}\n",
-                     g_arch.c_str(), v.prec, v.n, v.mb, v.h, v.wpb, ms, static_cast<long long>(points));
+        std::fprintf(f, "{\"arch\": \"%s\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"ms\": %.6f, \"points\": %lld}\n",
+                     g_arch.c_str(), v.prec, v.n, v.mb, v.h, v.cl, v.wpb, ms, static_cast<long long>(points));
         std::fclose(f);
     }
 }
 
-// Algorithmic flops per point of the tree schedule with unrolled depth mb and
-// h helicities per walk (FMA = 2; add, multiply, reciprocal = 1):
-//   node: q update 4, q^2 5, 1/q^2 1, scale by d 4 (= 14, shared by the walk's
-//         helicities) + per helicity 8 three-term complex products (= 40)
-//   closing: 10 + 2 FP64 adds per helicity
-//   vertex block build: 3 + 4 per helicity
+// Algorithmic flops per point of the schedule with unrolled depth mb, h
+// helicities per walk and closing depth cl (FMA = 2; add, multiply,
+// reciprocal = 1).  The h helicity configurations of one walk differ only in
+// the helicities of photons 0 .. log2(h)-1 (the "variant" photons).  Where
+// every index is a compile-time constant (n <= mb: the whole tree is one
+// unrolled subtree) a value that does not depend on a variant photon is the
+// same for all h configurations and is computed once: a current whose prefix
+// holds k variant photons has 2^k distinct values, a vertex block or pair
+// vector 2^(number of variant photons it involves).  Where the photons sit in
+// run-time slots (n > mb) nothing is shared and every value is counted h
+// times.  This is what the code computes when the compiler shares every
+// such value, so the count is a lower bound of the work executed.
+//   node update: q update 4, q^2 5, 1/q^2 1, scale by d 4 (= 14, once per node)
+//                + 40 per distinct current (8 three-term complex products)
+//   cl = 1 leaf: closing 10 + 2 FP64 adds per helicity
+//   cl = 2, node with two photons left: 2-vector product 14 + 2 FP64 adds per
+//         helicity; per subtree: per slot r, p1 - k_r 2, q^2 5, 1/q^2 1,
+//         scale 4 (= 12) and w_r 14 per distinct value, per ordered pair u_jr 20,
+//         per unordered pair U 4, per distinct value
+//   vertex block build: 3 + 4 per distinct value
 //   |ordering sum|^2 in FP64: 4 per helicity
-double me2_flops_per_point(int n, int mb, int h)
-{
-    const double H = h;
-    const double walks = double(1 << n) / H;
-    const double nfact = factorial(n);
-    double nodes = 0.0;  // sum_{j=1}^{n-1} n!/(n-j)!
-    for (int j = 1; j <= n - 1; ++j) nodes += nfact / factorial(n - j);
-    double builds = n;   // vertex blocks built per walk
-    if (n > mb) {
-        double top = 0.0;
-        for (int j = 1; j <= n - mb; ++j) top += nfact / factorial(n - j);
-        builds = top + nfact / factorial(mb) * mb;
+namespace flops {
+
+struct Walk {
+    int n, b, H, cl;
+    bool shared;
+    double total = 0.0;
+
+    int var_count(unsigned set) const  // distinct values over the walk's helicities
+    {
+        if (!shared) return H;
+        return 1 << __builtin_popcount(set & ((1u << b) - 1u));
     }
-    const double per_walk = nodes * (14.0 + 40.0 * H) + nfact * 12.0 * H + builds * (3.0 + 4.0 * H) +
-                            4.0 * H;
-    return walks * per_walk;
+
+    void subtree_pairs(unsigned slots)
+    {
+        for (int r = 0; r < n; ++r)
+            if (slots >> r & 1u) total += 12.0 + 14.0 * var_count(1u << r);
+        for (int j = 0; j < n; ++j)
+            for (int r = 0; r < n; ++r)
+                if (j != r && (slots >> j & 1u) && (slots >> r & 1u))
+                    total += 20.0 * var_count((1u << j) | (1u << r));
+        for (int j = 0; j < n; ++j)
+            for (int r = j + 1; r < n; ++r)
+                if ((slots >> j & 1u) && (slots >> r & 1u))
+                    total += 4.0 * var_count((1u << j) | (1u << r));
+    }
+
+    // walk below a node whose prefix used the photons in `used`
+    void below(unsigned used, int mb)
+    {
+        const unsigned all = (1u << n) - 1u;
+        const unsigned left = all & ~used;
+        const int nleft = __builtin_popcount(left);
+        if (nleft == mb || (used == 0 && n <= mb)) {
+            // subtree entry: vertex blocks of its slots, pair vectors
+            for (int s = 0; s < n; ++s)
+                if (left >> s & 1u) total += 3.0 + 4.0 * var_count(1u << s);
+            if (cl == 2) subtree_pairs(left);
+        }
+        if (cl == 1 && nleft == 1) {
+            total += 12.0 * H;
+            return;
+        }
+        if (cl == 2 && nleft == 2) {
+            total += 16.0 * H;
+            return;
+        }
+        for (int s = 0; s < n; ++s) {
+            if (!(left >> s & 1u)) continue;
+            if (nleft > mb) total += 3.0 + 4.0 * H;  // top-level node builds its vertex block
+            const unsigned u = used | (1u << s);
+            total += 14.0 + 40.0 * var_count(u);
+            below(u, mb);
+        }
+    }
+};
+
+}  // namespace flops
+
+double me2_flops_per_point(int n, int mb, int h, int cl)
+{
+    flops::Walk w;
+    w.n = n;
+    w.H = h;
+    w.b = 0;
+    while ((1 << w.b) < h) ++w.b;
+    w.cl = cl;
+    w.shared = n <= mb;
+    w.below(0u, n <= mb ? n : mb);
+    w.total += 4.0 * h;
+    return w.total * double(1 << n) / double(h);
 }
 
 // ---------------------------------------------------------------- timing hooks
@@ -426,8 +508,10 @@ void xsec_finish(void *p)
     delete t;
 }
 
-heget_status xsec_enqueue(int n, const heget_config *cfg, heget_result *out, hipStream_t s,
-                          unsigned **flags_out)
+// Enqueue the whole path.  The result goes to d_out (device-writable, filled by
+// a kernel) when given, else to *out through the pinned ring and a host callback.
+heget_status xsec_enqueue(int n, const heget_config *cfg, heget_result *out, heget_result *d_out,
+                          hipStream_t s, unsigned **flags_out)
 {
     const int64_t np = cfg->npoints;
     const int nb = static_cast<int>((np + 255) / 256);
@@ -481,12 +565,17 @@ heget_status xsec_enqueue(int n, const heget_config *cfg, heget_result *out, hip
         HG_HIP(heget::launch_sum_chunks(part, nchunks, np, d_count, np, me2, flags, s));
     HG_HIP(heget::launch_weights(me2, index, wfac, d_count, np, partials, flags, s));
     HG_HIP(heget::launch_final(partials, nb, d_count, res, s));
-    const unsigned slot = g.ring.fetch_add(1) % kRing;
-    double *staged = g.pinned + 8 * slot;
-    HG_HIP(hipMemcpyAsync(staged, res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HG_TRY(scratch_release(s));
-    XsecTicket *t = new XsecTicket{out, staged, np};
-    HG_HIP(hipLaunchHostFunc(s, xsec_finish, t));
+    if (d_out) {
+        HG_HIP(heget::launch_result(res, np, d_out, s));
+        HG_TRY(scratch_release(s));
+    } else {
+        const unsigned slot = g.ring.fetch_add(1) % kRing;
+        double *staged = g.pinned + 8 * slot;
+        HG_HIP(hipMemcpyAsync(staged, res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HG_TRY(scratch_release(s));
+        XsecTicket *t = new XsecTicket{out, staged, np};
+        HG_HIP(hipLaunchHostFunc(s, xsec_finish, t));
+    }
     if (flags_out) *flags_out = flags;
     return HEGET_OK;
 }
@@ -513,11 +602,11 @@ struct SliceBufs {
     uint8_t *flag;
     int32_t *bcount, *offs, *index;
     int64_t *d_count;
-    int nb, nchunks, mb, h;
+    int nb, nchunks, mb, h, cl;
 };
 
-void carve_batch(Arena &ar, int ncfg, const int *n, const heget_config *cfgs, SliceBufs *sb,
-                 unsigned **flags, unsigned long long **queue, int64_t **item_start)
+void carve_batch(Arena &ar, int ncfg, const int *n, const heget_config *cfgs, int schedule,
+                 SliceBufs *sb, unsigned **flags, unsigned long long **queue, int64_t **item_start)
 {
     *flags = ar.take<unsigned>(1);
     *queue = ar.take<unsigned long long>(1);
@@ -525,9 +614,16 @@ void carve_batch(Arena &ar, int ncfg, const int *n, const heget_config *cfgs, Sl
     for (int s = 0; s < ncfg; ++s) {
         const int64_t np = cfgs[s].npoints;
         SliceBufs &b = sb[s];
-        heget::me2_batch_shape(cfgs[s].prec, n[s], &b.mb, &b.h);
+        if (schedule == 1) {
+            heget::me2_batch_shape(cfgs[s].prec, n[s], &b.mb, &b.h, &b.cl);
+        } else {
+            const heget::Me2Variant *v = pick_variant(cfgs[s].prec, n[s]);
+            b.mb = v->mb;
+            b.h = v->h;
+            b.cl = v->cl;
+        }
         b.nb = static_cast<int>((np + 255) / 256);
-        b.nchunks = plan_chunks_shape(n[s], b.mb, b.h, np / 2);
+        b.nchunks = plan_chunks_shape(n[s], b.mb, b.h, b.cl, np / 2);
         b.mom = ar.take<double>(size_t(n[s] + 2) * 4 * size_t(np));
         b.wfac = ar.take<double>(size_t(np));
         b.flag = ar.take<uint8_t>(size_t(np));
@@ -540,6 +636,57 @@ void carve_batch(Arena &ar, int ncfg, const int *n, const heget_config *cfgs, Sl
         b.partials = ar.take<double>(size_t(3) * b.nb);
         b.res = ar.take<double>(4);
     }
+}
+
+heget::GenParams slice_gen_params(int n, const heget_config &c)
+{
+    heget::GenParams gp{};
+    gp.mode = c.mode;
+    gp.seed = c.seed;
+    gp.npoints = c.npoints;
+    gp.sqrt_s = c.sqrt_s;
+    gp.lo = c.sqrt_shat_lo;
+    gp.hi = c.sqrt_shat_hi;
+    gp.pt_min = c.cuts.pt_min;
+    gp.eta_max = c.cuts.eta_max;
+    gp.dr_min = c.cuts.dr_min;
+    gp.partonic_coef = partonic_coef(n);
+    gp.phase_volume_coef = phase_volume_coef(n);
+    gp.weight_kind = 1;
+    return gp;
+}
+
+// Parallel schedule: one fork/join branch per configuration on the side
+// streams, each with the tuned amplitude kernel for its n.
+heget_status batch_enqueue_branches(int ncfg, const int *n, const heget_config *cfgs, SliceBufs *sb,
+                                    unsigned *flags, double *staged, hipStream_t s)
+{
+    HG_HIP(heget::launch_zero_u32(flags, 1, s));
+    HG_HIP(hipEventRecord(g.fork, s));
+    for (int i = 0; i < ncfg; ++i) {
+        hipStream_t si = g.side[i];
+        const heget_config &c = cfgs[i];
+        SliceBufs &b = sb[i];
+        const int64_t np = c.npoints;
+        HG_HIP(hipStreamWaitEvent(si, g.fork, 0));
+        HG_HIP(heget::launch_gen(n[i], slice_gen_params(n[i], c), b.mom, np, b.wfac, b.flag, b.bcount, si));
+        HG_HIP(heget::launch_scan(b.bcount, b.nb, b.offs, b.d_count, si));
+        HG_HIP(heget::launch_compact(b.flag, np, b.offs, b.index, si));
+        const heget::Me2Variant *v = pick_variant(c.prec, n[i]);
+        heget::Me2Args ma{b.mom, np, b.index, b.d_count, np, b.nchunks,
+                          me2_coef(n[i], c.alpha, c.charge), b.part, np, flags};
+        HG_HIP(heget::launch_me2(*v, ma, si));
+        if (b.nchunks > 1)
+            HG_HIP(heget::launch_sum_chunks(b.part, b.nchunks, np, b.d_count, np, b.me2, flags, si));
+        HG_HIP(heget::launch_weights(b.me2, b.index, b.wfac, b.d_count, np, b.partials, flags, si));
+        HG_HIP(heget::launch_final(b.partials, b.nb, b.d_count, b.res, si));
+        HG_HIP(hipMemcpyAsync(staged + 4 * i, b.res, 4 * sizeof(double), hipMemcpyDeviceToHost, si));
+        HG_HIP(hipEventRecord(g.join[i], si));
+        HG_HIP(hipStreamWaitEvent(s, g.join[i], 0));
+    }
+    HG_HIP(hipMemcpyAsync(staged + 4 * heget::kMaxSlices, flags, sizeof(unsigned),
+                          hipMemcpyDeviceToHost, s));
+    return HEGET_OK;
 }
 
 heget_status batch_enqueue(int ncfg, const int *n, const heget_config *cfgs, SliceBufs *sb,
@@ -572,8 +719,8 @@ heget_status batch_enqueue(int ncfg, const int *n, const heget_config *cfgs, Sli
     std::vector<int> order(ncfg);
     for (int i = 0; i < ncfg; ++i) order[i] = i;
     std::sort(order.begin(), order.end(), [&](int x, int y) {
-        const double cx = me2_flops_per_point(n[x], sb[x].mb, sb[x].h) / sb[x].nchunks;
-        const double cy = me2_flops_per_point(n[y], sb[y].mb, sb[y].h) / sb[y].nchunks;
+        const double cx = me2_flops_per_point(n[x], sb[x].mb, sb[x].h, sb[x].cl) / sb[x].nchunks;
+        const double cy = me2_flops_per_point(n[y], sb[y].mb, sb[y].h, sb[y].cl) / sb[y].nchunks;
         return cx > cy || (cx == cy && x < y);
     });
     heget::BatchDesc bd{};
@@ -627,6 +774,64 @@ heget_result make_result(const double *st, int64_t n_gen)
     const double var = n_gen > 1 ? (sum2 / double(n_gen) - r.sigma_fb * r.sigma_fb) / double(n_gen - 1) : 0.0;
     r.err_fb = std::sqrt(var > 0.0 ? var : 0.0);
     return r;
+}
+
+// Capture the batch for one schedule into an executable graph.
+heget_status capture_batch(int schedule, int ncfg, const int *n, const heget_config *cfgs,
+                           double *staged, hipStream_t s, hipGraphExec_t *exec)
+{
+    SliceBufs sb[heget::kMaxSlices];
+    unsigned *flags;
+    unsigned long long *queue;
+    int64_t *item_start;
+    Arena sizing;
+    carve_batch(sizing, ncfg, n, cfgs, schedule, sb, &flags, &queue, &item_start);
+    void *base = nullptr;
+    HG_TRY(scratch(S_BATCH, sizing.off, &base));
+    Arena ar;
+    ar.base = static_cast<char *>(base);
+    carve_batch(ar, ncfg, n, cfgs, schedule, sb, &flags, &queue, &item_start);
+    HG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    heget_status st = schedule == 1
+                          ? batch_enqueue(ncfg, n, cfgs, sb, flags, queue, item_start, staged, s)
+                          : batch_enqueue_branches(ncfg, n, cfgs, sb, flags, staged, s);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (st < 0) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    HG_HIP(e);
+    e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HG_HIP(e);
+    return HEGET_OK;
+}
+
+heget_status ensure_side_streams()
+{
+    if (g.fork) return HEGET_OK;
+    HG_HIP(hipEventCreateWithFlags(&g.fork, hipEventDisableTiming));
+    for (int i = 0; i < heget::kMaxSlices; ++i) {
+        HG_HIP(hipStreamCreateWithFlags(&g.side[i], hipStreamNonBlocking));
+        HG_HIP(hipEventCreateWithFlags(&g.join[i], hipEventDisableTiming));
+    }
+    return HEGET_OK;
+}
+
+heget_status time_graph(hipGraphExec_t exec, hipStream_t s, float *ms)
+{
+    hipEvent_t e0, e1;
+    HG_HIP(hipEventCreate(&e0));
+    HG_HIP(hipEventCreate(&e1));
+    HG_HIP(hipEventRecord(e0, s));
+    HG_HIP(hipGraphLaunch(exec, s));
+    HG_HIP(hipEventRecord(e1, s));
+    HG_HIP(hipEventSynchronize(e1));
+    HG_HIP(hipEventElapsedTime(ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return HEGET_OK;
 }
 
 }  // namespace
@@ -775,7 +980,19 @@ heget_status heget_xsec_async(int n, const heget_config *cfg, heget_result *out,
     }
     std::lock_guard<std::mutex> lk(g_mu);
     HG_TRY(ensure_device());
-    return xsec_enqueue(n, cfg, out, static_cast<hipStream_t>(stream), nullptr);
+    return xsec_enqueue(n, cfg, out, nullptr, static_cast<hipStream_t>(stream), nullptr);
+}
+
+heget_status heget_xsec_device(int n, const heget_config *cfg, heget_result *d_out,
+                               heget_stream stream)
+{
+    g_err.clear();
+    HG_TRY(check_config(n, cfg));
+    if (!d_out) return fail(HEGET_ERR_ARG, "d_out is NULL");
+    if (cfg->npoints == 0) return fail(HEGET_ERR_RANGE, "heget_xsec_device needs npoints > 0");
+    std::lock_guard<std::mutex> lk(g_mu);
+    HG_TRY(ensure_device());
+    return xsec_enqueue(n, cfg, nullptr, d_out, static_cast<hipStream_t>(stream), nullptr);
 }
 
 heget_status heget_xsec(int n, const heget_config *cfg, heget_result *out)
@@ -790,7 +1007,7 @@ heget_status heget_xsec(int n, const heget_config *cfg, heget_result *out)
     std::lock_guard<std::mutex> lk(g_mu);
     HG_TRY(ensure_device());
     unsigned *d_flags = nullptr;
-    HG_TRY(xsec_enqueue(n, cfg, out, g.stream, &d_flags));
+    HG_TRY(xsec_enqueue(n, cfg, out, nullptr, g.stream, &d_flags));
     unsigned flags = 0;
     HG_HIP(hipMemcpyAsync(&flags, d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, g.stream));
     HG_HIP(hipStreamSynchronize(g.stream));
@@ -801,7 +1018,18 @@ heget_status heget_xsec(int n, const heget_config *cfg, heget_result *out)
     return HEGET_OK;
 }
 
-heget_status heget_xsec_batch(const int *n, const heget_config *cfgs, int ncfg, heget_result *out)
+heget_status heget_set_batch_schedule(int schedule)
+{
+    g_err.clear();
+    if (schedule < 0 || schedule > 2) return fail(HEGET_ERR_ARG, "schedule must be 0, 1 or 2");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g.batch_schedule = schedule;
+    drop_graphs();
+    return HEGET_OK;
+}
+
+heget_status heget_xsec_batch(const int *n, const heget_config *cfgs, int ncfg,
+                                         heget_result *out)
 {
     g_err.clear();
     if (!n || !cfgs || !out) return fail(HEGET_ERR_ARG, "null pointer");
@@ -820,21 +1048,8 @@ heget_status heget_xsec_batch(const int *n, const heget_config *cfgs, int ncfg, 
     }
     std::lock_guard<std::mutex> lk(g_mu);
     HG_TRY(ensure_device());
+    HG_TRY(ensure_side_streams());
     hipStream_t s = g.stream;
-    // sizes first, then the arena
-    SliceBufs sb[heget::kMaxSlices];
-    unsigned *flags;
-    unsigned long long *queue;
-    int64_t *item_start;
-    Arena sizing;
-    carve_batch(sizing, ncfg, n, cfgs, sb, &flags, &queue, &item_start);
-    void *base = nullptr;
-    HG_TRY(scratch(S_BATCH, sizing.off, &base));
-    Arena ar;
-    ar.base = static_cast<char *>(base);
-    carve_batch(ar, ncfg, n, cfgs, sb, &flags, &queue, &item_start);
-
-    const bool use_graph = std::getenv("HEGET_NO_GRAPH") == nullptr;
     const std::string key = batch_key(ncfg, n, cfgs);
     BatchGraph *bg = nullptr;
     for (BatchGraph &b : g_graphs)
@@ -842,28 +1057,31 @@ heget_status heget_xsec_batch(const int *n, const heget_config *cfgs, int ncfg, 
     HG_TRY(scratch_acquire(s));
     if (!bg) {
         if (g_graphs.size() >= 8) drop_graphs();
-        g_graphs.push_back(BatchGraph{});
-        bg = &g_graphs.back();
-        bg->key = key;
-        HG_HIP(hipHostMalloc(reinterpret_cast<void **>(&bg->staged),
+        BatchGraph nb;
+        nb.key = key;
+        HG_HIP(hipHostMalloc(reinterpret_cast<void **>(&nb.staged),
                              sizeof(double) * 4 * (heget::kMaxSlices + 1), hipHostMallocDefault));
-        if (use_graph) {
-            HG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            heget_status st = batch_enqueue(ncfg, n, cfgs, sb, flags, queue, item_start, bg->staged, s);
-            hipGraph_t graph = nullptr;
-            hipError_t e = hipStreamEndCapture(s, &graph);
-            if (st < 0) return st;
-            HG_HIP(e);
-            e = hipGraphInstantiate(&bg->exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            HG_HIP(e);
+        if (g.batch_schedule == 0) {
+            // auto: capture both schedules, keep the faster (one timed run each)
+            hipGraphExec_t a1 = nullptr, a2 = nullptr;
+            HG_TRY(capture_batch(1, ncfg, n, cfgs, nb.staged, s, &a1));
+            HG_TRY(capture_batch(2, ncfg, n, cfgs, nb.staged, s, &a2));
+            HG_HIP(hipGraphLaunch(a1, s));  // warm both
+            HG_HIP(hipGraphLaunch(a2, s));
+            float t1 = 0.f, t2 = 0.f;
+            HG_TRY(time_graph(a1, s, &t1));
+            HG_TRY(time_graph(a2, s, &t2));
+            nb.schedule = t1 <= t2 ? 1 : 2;
+            nb.exec = t1 <= t2 ? a1 : a2;
+            (void)hipGraphExecDestroy(t1 <= t2 ? a2 : a1);
+        } else {
+            nb.schedule = g.batch_schedule;
+            HG_TRY(capture_batch(nb.schedule, ncfg, n, cfgs, nb.staged, s, &nb.exec));
         }
+        g_graphs.push_back(nb);
+        bg = &g_graphs.back();
     }
-    if (bg->exec) {
-        HG_HIP(hipGraphLaunch(bg->exec, s));
-    } else {
-        HG_TRY(batch_enqueue(ncfg, n, cfgs, sb, flags, queue, item_start, bg->staged, s));
-    }
+    HG_HIP(hipGraphLaunch(bg->exec, s));
     HG_TRY(scratch_release(s));
     HG_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < ncfg; ++i) out[i] = make_result(bg->staged + 4 * i, cfgs[i].npoints);
@@ -876,8 +1094,22 @@ heget_status heget_xsec_batch(const int *n, const heget_config *cfgs, int ncfg, 
     return HEGET_OK;
 }
 
-heget_status heget_autotune(int n, heget_prec prec, int64_t npoints, int *unrolled,
-                            int *helicities_per_walk, int *waves_per_block, double *ms)
+heget_status heget_batch_schedule_in_use(const int *n, const heget_config *cfgs,
+                                                    int ncfg, int *schedule)
+{
+    g_err.clear();
+    if (!n || !cfgs || !schedule || ncfg < 1 || ncfg > heget::kMaxSlices)
+        return fail(HEGET_ERR_ARG, "bad arguments");
+    std::lock_guard<std::mutex> lk(g_mu);
+    const std::string key = batch_key(ncfg, n, cfgs);
+    *schedule = 0;
+    for (BatchGraph &b : g_graphs)
+        if (b.key == key) *schedule = b.schedule;
+    return HEGET_OK;
+}
+
+heget_status heget_autotune(int n, heget_prec prec, int64_t npoints, heget_shape *chosen,
+                            double *ms)
 {
     g_err.clear();
     HG_TRY(check_n(n));
@@ -942,53 +1174,45 @@ heget_status heget_autotune(int n, heget_prec prec, int64_t npoints, int *unroll
     if (!best) return fail(HEGET_ERR_ARG, "no compiled amplitude kernel for this n/precision");
     g_tuned[prec][n] = best;
     save_tuning_cache(*best, best_ms, npoints);
-    if (unrolled) *unrolled = best->mb;
-    if (helicities_per_walk) *helicities_per_walk = best->h;
-    if (waves_per_block) *waves_per_block = best->wpb;
+    if (chosen) *chosen = shape_of(*best);
     if (ms) *ms = best_ms;
     return HEGET_OK;
 }
 
-heget_status heget_set_kernel_shape(int n, heget_prec prec, int mb, int h, int wpb)
+heget_status heget_set_kernel_shape(int n, heget_prec prec, const heget_shape *shape)
 {
     g_err.clear();
     HG_TRY(check_n(n));
     HG_TRY(check_prec(prec));
     std::lock_guard<std::mutex> lk(g_mu);
-    if (mb == 0 && h == 0 && wpb == 0) {
+    if (!shape) {
         g_tuned[prec][n] = nullptr;
         return HEGET_OK;
     }
-    const heget::Me2Variant *v = find_variant(prec, n, mb, h, wpb);
+    const heget::Me2Variant *v =
+        find_variant(prec, n, shape->unrolled, shape->helicities_per_walk, shape->closing,
+                     shape->waves_per_block);
     if (!v) return fail(HEGET_ERR_ARG, "no compiled kernel shape with these parameters");
     g_tuned[prec][n] = v;
     return HEGET_OK;
 }
 
-heget_status heget_kernel_shapes(int n, heget_prec prec, int max, int *mb, int *h, int *wpb,
-                                 int *count)
+heget_status heget_kernel_shapes(int n, heget_prec prec, int max, heget_shape *shapes, int *count)
 {
     g_err.clear();
     HG_TRY(check_n(n));
     HG_TRY(check_prec(prec));
-    if (!count) return fail(HEGET_ERR_ARG, "null pointer");
+    if (!count || (max > 0 && !shapes)) return fail(HEGET_ERR_ARG, "null pointer");
     int cnt = 0, k = 0;
     const heget::Me2Variant *all = heget::me2_variants(&cnt);
     const heget::Me2Variant *cur = pick_variant(prec, n);
-    // the shape in use first
-    if (cur && k < max && mb && h && wpb) {
-        mb[k] = cur->mb;
-        h[k] = cur->h;
-        wpb[k] = cur->wpb;
+    if (cur) {  // the shape in use first
+        if (k < max) shapes[k] = shape_of(*cur);
+        ++k;
     }
-    if (cur) ++k;
     for (int i = 0; i < cnt; ++i) {
         if (all[i].prec != prec || all[i].n != n || &all[i] == cur) continue;
-        if (k < max && mb && h && wpb) {
-            mb[k] = all[i].mb;
-            h[k] = all[i].h;
-            wpb[k] = all[i].wpb;
-        }
+        if (k < max) shapes[k] = shape_of(all[i]);
         ++k;
     }
     *count = k;
@@ -1029,8 +1253,7 @@ heget_status heget_timing_read(double *me2_ms, int64_t *me2_launches, int reset)
     return HEGET_OK;
 }
 
-heget_status heget_me2_flops(int n, heget_prec prec, double *flops_per_point, int *unrolled,
-                             int *helicities_per_walk)
+heget_status heget_me2_flops(int n, heget_prec prec, double *flops_per_point, heget_shape *shape)
 {
     g_err.clear();
     HG_TRY(check_n(n));
@@ -1038,9 +1261,8 @@ heget_status heget_me2_flops(int n, heget_prec prec, double *flops_per_point, in
     if (!flops_per_point) return fail(HEGET_ERR_ARG, "null pointer");
     const heget::Me2Variant *v = pick_variant(prec, n);
     if (!v) return fail(HEGET_ERR_ARG, "no compiled amplitude kernel for this n/precision");
-    *flops_per_point = me2_flops_per_point(n, v->mb, v->h);
-    if (unrolled) *unrolled = v->mb;
-    if (helicities_per_walk) *helicities_per_walk = v->h;
+    *flops_per_point = me2_flops_per_point(n, v->mb, v->h, v->cl);
+    if (shape) *shape = shape_of(*v);
     return HEGET_OK;
 }
 
@@ -1059,6 +1281,14 @@ void heget_shutdown(void)
     g.ev.clear();
     g.ev_used = 0;
     drop_graphs();
+    for (int i = 0; i < 8; ++i) {
+        if (g.side[i]) (void)hipStreamDestroy(g.side[i]);
+        if (g.join[i]) (void)hipEventDestroy(g.join[i]);
+        g.side[i] = nullptr;
+        g.join[i] = nullptr;
+    }
+    if (g.fork) (void)hipEventDestroy(g.fork);
+    g.fork = nullptr;
     if (g.pinned) (void)hipHostFree(g.pinned);
     g.pinned = nullptr;
     if (g.ws_free) (void)hipEventDestroy(g.ws_free);

@@ -14,6 +14,7 @@ struct Me2Variant {
     int n;      // photons
     int mb;     // unrolled bottom levels (photons held in registers)
     int h;      // helicity configurations per tree walk
+    int cl;     // closing depth: 1 = photon by photon, 2 = last pair by pair vectors
     int wpb;    // waves per block
     const void *func;  // kernel symbol
 };
@@ -65,8 +66,8 @@ hipError_t launch_batch_plan(const BatchDesc &b, hipStream_t stream);
 // prec 0 = FP64, 1 = FP32; grid = number of persistent blocks of 256 threads.
 hipError_t launch_me2_batch(int prec, const BatchDesc &b, int grid, hipStream_t stream);
 int me2_batch_blocks_per_cu(int prec);
-// default (unrolled depth, helicities per walk) of the mixed kernel for n
-void me2_batch_shape(int prec, int n, int *mb, int *h);
+// (unrolled depth, helicities per walk, closing depth) of the mixed kernel for n
+void me2_batch_shape(int prec, int n, int *mb, int *h, int *cl);
 
 // Phase-space generation (FP64): momenta in SoA, weight (kind 0: Phi_n; kind
 // 1: full eq. (1)-(2) factor without |M|^2), accept flag, per-block accept
@@ -90,6 +91,9 @@ hipError_t launch_weights(const double *me2, const int32_t *index, const double 
 // (sum, compensation, sum of squares) and res[3] = (double)*d_count.
 hipError_t launch_final(const double *partials, int nb, const int64_t *d_count, double *res,
                         hipStream_t stream);
+// Result record {sigma, err, sum, comp, sum2 (double), n_gen, n_acc (int64)}
+// from res[0..3] = (sum, comp, sum2, n_acc) and n_gen, written to out.
+hipError_t launch_result(const double *res, int64_t n_gen, void *out, hipStream_t stream);
 // Zero a small device buffer with a kernel (usable under stream capture).
 hipError_t launch_zero_u32(unsigned *p, int count, hipStream_t stream);
 

@@ -207,6 +207,25 @@ final_kernel(const double *__restrict__ partials, int nb, const int64_t *__restr
     }
 }
 
+// sigma = sum/N and its MC error written as the heget_result layout
+// {sigma, err, sum, comp, sum2, n_gen, n_acc} (five doubles, two int64).
+__global__ void result_kernel(const double *__restrict__ res, int64_t n_gen, void *out)
+{
+    double *d = static_cast<double *>(out);
+    int64_t *q = static_cast<int64_t *>(out);
+    const double sum = res[0], sum2 = res[2];
+    const double N = static_cast<double>(n_gen);
+    const double sigma = n_gen > 0 ? sum / N : 0.0;
+    const double var = n_gen > 1 ? (sum2 / N - sigma * sigma) / (N - 1.0) : 0.0;
+    d[0] = sigma;
+    d[1] = sqrt(var > 0.0 ? var : 0.0);
+    d[2] = sum;
+    d[3] = res[1];
+    d[4] = sum2;
+    q[5] = n_gen;
+    q[6] = static_cast<int64_t>(res[3]);
+}
+
 __global__ void zero_u32_kernel(unsigned *p, int count)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -283,6 +302,12 @@ hipError_t launch_final(const double *partials, int nb, const int64_t *d_count, 
                         hipStream_t stream)
 {
     hipLaunchKernelGGL(final_kernel, dim3(1), dim3(256), 0, stream, partials, nb, d_count, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_result(const double *res, int64_t n_gen, void *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(result_kernel, dim3(1), dim3(1), 0, stream, res, n_gen, out);
     return hipGetLastError();
 }
 

@@ -1,0 +1,59 @@
+// Registry of the compiled amplitude-kernel shapes and their launcher.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace heget {
+
+// Tables defined in the me2_shapes_*.hip translation units.
+extern const Me2Variant kShapesF32Lo[], kShapesF32Mid[], kShapesF32Hi[];
+extern const Me2Variant kShapesF64Lo[], kShapesF64Mid[], kShapesF64Hi[];
+extern const int kShapesF32LoCount, kShapesF32MidCount, kShapesF32HiCount;
+extern const int kShapesF64LoCount, kShapesF64MidCount, kShapesF64HiCount;
+
+static const std::vector<Me2Variant> &all_variants()
+{
+    static const std::vector<Me2Variant> v = [] {
+        std::vector<Me2Variant> r;
+        const Me2Variant *tabs[] = {kShapesF32Lo, kShapesF32Mid, kShapesF32Hi,
+                                    kShapesF64Lo, kShapesF64Mid, kShapesF64Hi};
+        const int counts[] = {kShapesF32LoCount, kShapesF32MidCount, kShapesF32HiCount,
+                              kShapesF64LoCount, kShapesF64MidCount, kShapesF64HiCount};
+        for (int t = 0; t < 6; ++t)
+            for (int i = 0; i < counts[t]; ++i) r.push_back(tabs[t][i]);
+        return r;
+    }();
+    return v;
+}
+
+const Me2Variant *me2_variants(int *count)
+{
+    *count = static_cast<int>(all_variants().size());
+    return all_variants().data();
+}
+
+const Me2Variant *me2_default(int prec, int n)
+{
+    for (const Me2Variant &v : all_variants())
+        if (v.prec == prec && v.n == n) return &v;
+    return nullptr;
+}
+
+hipError_t launch_me2(const Me2Variant &v, const Me2Args &a, hipStream_t stream)
+{
+    const int64_t ntiles = (a.count + 63) / 64;
+    const int64_t items = ntiles * a.nchunks;
+    if (items == 0) return hipSuccess;
+    const int64_t blocks = (items + v.wpb - 1) / v.wpb;
+    void *args[] = {const_cast<double **>(&a.mom), const_cast<int64_t *>(&a.ld),
+                    const_cast<int32_t **>(&a.index), const_cast<int64_t **>(&a.d_count),
+                    const_cast<int64_t *>(&a.count), const_cast<int *>(&a.nchunks),
+                    const_cast<double *>(&a.coef), const_cast<double **>(&a.out),
+                    const_cast<int64_t *>(&a.ld_out), const_cast<unsigned **>(&a.flags)};
+    return hipLaunchKernel(v.func, dim3(static_cast<unsigned>(blocks)), dim3(v.wpb * 64), args, 0,
+                           stream);
+}
+
+}  // namespace heget

@@ -42,6 +42,17 @@
 //    q starts at -p2 (HELAS stores the ubar momentum times nSF = -1).
 //  * Momenta are scaled by an exact power of two 2^-m with 2^m ~ E1 + E2, so
 //    FP32 values stay near 1; |M(p)|^2 = 2^(2m(2-n)) |M(2^-m p)|^2.
+//  * Pair closing (CL = 2), the two-sided current reuse of the MadGraph
+//    program of Appendix A.1 applied to the last two photons: before the last
+//    photon r the current carries momentum p1 - k_r whatever the ordering, so
+//    the last update plus closing of ordering (.., j, r) is a fixed row vector
+//        u_jr = c_r d(p1 - k_r) P(p1 - k_r) V_j,   c_r = (gamma_r, -a3_r),
+//    i.e. the incoming current from the u end after photon r (fvixx0) met at
+//    the vertex of photon j.  The two orderings of a remaining pair {j, r}
+//    close with U_jr = u_jr + u_rj, so a node with two photons left ends the
+//    walk with one 2-vector product and the n! last-level updates disappear.
+//    p1 - k_r is formed from p1 directly, free of the cancellation the
+//    incremental sum from -p2 carries for photons close to the beam.
 //
 // Tree layout on the device.  The bottom MB levels of the tree (the subtree
 // below a node with MB photons left) are unrolled at compile time with the
@@ -90,6 +101,15 @@ struct Slots {
     LMom<R> k[NS];
     Vert<R, H> v[NS];
 };
+
+// Pair-closing row vectors U_ab (a < b) for the slot photons, per variant.
+template <typename R, int H, int NS>
+struct PairTab {
+    R u1r[NS][NS][H], u1i[NS][NS][H], u2r[NS][NS][H], u2i[NS][NS][H];
+};
+
+// Unused placeholder when the walk closes photon by photon (CL = 1).
+struct NoPairs {};
 
 // V'(lam) of photon j for the H variants whose helicity configurations are
 // cfg0 .. cfg0+H-1 (bit j set = helicity +1).  cfg0 is wave-uniform.
@@ -185,13 +205,83 @@ __device__ __forceinline__ void for_each_bit(F &&f)
     }
 }
 
-// Unrolled subtree over the slot photons in MASK, entered with current c at momentum q.
-template <typename R, int H, int NS, unsigned MASK>
-__device__ __forceinline__ void subtree(const Slots<R, H, NS> &S, const Chain<R, H> &c,
+// Pair vectors of the slot photons: w_r = c_r d(q_r) P(q_r) with q_r = p1 - k_r,
+// u_jr = w_r V_j, U_jr = u_jr + u_rj.
+template <typename R, int H, int NS>
+__device__ __forceinline__ void make_pairs(const Slots<R, H, NS> &S, const LMom<R> &p1,
+                                           PairTab<R, H, NS> &T)
+{
+    R w1r[NS][H], w1i[NS][H], w2r[NS][H], w2i[NS][H];
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+        LMom<R> q;
+        q.p = p1.p - S.k[r].p;
+        q.m = p1.m - S.k[r].m;
+        q.x = -S.k[r].x;
+        q.y = -S.k[r].y;
+        const R q2 = q.p * q.m - q.x * q.x - q.y * q.y;
+        const R d = neg_recip(q2);
+        const R Pm = d * q.m, Pp = d * q.p, Px = d * q.x, Py = d * q.y;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const R gr = S.v[r].gr[h], gi = S.v[r].gi[h], a3 = S.v[r].a3[h];
+            w1r[r][h] = gr * Pm + a3 * Px;
+            w1i[r][h] = gi * Pm - a3 * Py;
+            w2r[r][h] = -(gr * Px - gi * Py) - a3 * Pp;
+            w2i[r][h] = -(gr * Py + gi * Px);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NS; ++a)
+#pragma unroll
+        for (int b = a + 1; b < NS; ++b)
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                // u_ab = w_b V_a and u_ba = w_a V_b; V = [[a3, beta], [gamma, -a3]]
+                const Vert<R, H> &va = S.v[a], &vb = S.v[b];
+                const R x1r = w1r[b][h] * va.a3[h] + w2r[b][h] * va.gr[h] - w2i[b][h] * va.gi[h];
+                const R x1i = w1i[b][h] * va.a3[h] + w2r[b][h] * va.gi[h] + w2i[b][h] * va.gr[h];
+                const R x2r = w1r[b][h] * va.br[h] - w1i[b][h] * va.bi[h] - w2r[b][h] * va.a3[h];
+                const R x2i = w1r[b][h] * va.bi[h] + w1i[b][h] * va.br[h] - w2i[b][h] * va.a3[h];
+                const R y1r = w1r[a][h] * vb.a3[h] + w2r[a][h] * vb.gr[h] - w2i[a][h] * vb.gi[h];
+                const R y1i = w1i[a][h] * vb.a3[h] + w2r[a][h] * vb.gi[h] + w2i[a][h] * vb.gr[h];
+                const R y2r = w1r[a][h] * vb.br[h] - w1i[a][h] * vb.bi[h] - w2r[a][h] * vb.a3[h];
+                const R y2i = w1r[a][h] * vb.bi[h] + w1i[a][h] * vb.br[h] - w2i[a][h] * vb.a3[h];
+                T.u1r[a][b][h] = x1r + y1r;
+                T.u1i[a][b][h] = x1i + y1i;
+                T.u2r[a][b][h] = x2r + y2r;
+                T.u2i[a][b][h] = x2i + y2i;
+            }
+}
+
+// Close a node with slots a < b left: amp = U_ab . g, summed in FP64.
+template <typename R, int H, int NS>
+__device__ __forceinline__ void close_pair(const PairTab<R, H, NS> &T, int a, int b,
+                                           const Chain<R, H> &c, Acc<H> &acc)
+{
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const R ar = T.u1r[a][b][h] * c.g2r[h] - T.u1i[a][b][h] * c.g2i[h] +
+                     T.u2r[a][b][h] * c.g3r[h] - T.u2i[a][b][h] * c.g3i[h];
+        const R ai = T.u1r[a][b][h] * c.g2i[h] + T.u1i[a][b][h] * c.g2r[h] +
+                     T.u2r[a][b][h] * c.g3i[h] + T.u2i[a][b][h] * c.g3r[h];
+        acc.re[h] += static_cast<double>(ar);
+        acc.im[h] += static_cast<double>(ai);
+    }
+}
+
+// Unrolled subtree over the slot photons in MASK, entered with current c at
+// momentum q.  CL = 1 closes photon by photon; CL = 2 closes the last pair.
+template <typename R, int H, int NS, int CL, unsigned MASK, typename PT>
+__device__ __forceinline__ void subtree(const Slots<R, H, NS> &S, const PT &T, const Chain<R, H> &c,
                                         const LMom<R> &q, Acc<H> &acc)
 {
-    if constexpr (__builtin_popcount(MASK) == 1) {
+    if constexpr (CL == 1 && __builtin_popcount(MASK) == 1) {
         close_chain<R, H>(S.v[__builtin_ctz(MASK)], c, acc);
+    } else if constexpr (CL == 2 && __builtin_popcount(MASK) == 2) {
+        constexpr int a = __builtin_ctz(MASK);
+        constexpr int b = __builtin_ctz(MASK & (MASK - 1u));
+        close_pair<R, H, NS>(T, a, b, c, acc);
     } else {
         for_each_bit<MASK>([&](auto bit) {
             constexpr int s = decltype(bit)::value;
@@ -199,8 +289,22 @@ __device__ __forceinline__ void subtree(const Slots<R, H, NS> &S, const Chain<R,
             const Prop<R> P = propagate<R>(q, S.k[s], qn);
             Chain<R, H> cn;
             update<R, H>(S.v[s], c, P, cn);
-            subtree<R, H, NS, (MASK & ~(1u << s))>(S, cn, qn, acc);
+            subtree<R, H, NS, CL, (MASK & ~(1u << s))>(S, T, cn, qn, acc);
         });
+    }
+}
+
+// Enter a subtree over all NS slots (builds the pair vectors first for CL = 2).
+template <typename R, int H, int NS, int CL>
+__device__ __forceinline__ void run_subtree(const Slots<R, H, NS> &S, const LMom<R> &p1,
+                                            const Chain<R, H> &c, const LMom<R> &q, Acc<H> &acc)
+{
+    if constexpr (CL == 2) {
+        PairTab<R, H, NS> T;
+        make_pairs<R, H, NS>(S, p1, T);
+        subtree<R, H, NS, CL, (1u << NS) - 1u>(S, T, c, q, acc);
+    } else {
+        subtree<R, H, NS, CL, (1u << NS) - 1u>(S, NoPairs{}, c, q, acc);
     }
 }
 
@@ -215,9 +319,10 @@ __device__ __forceinline__ LMom<R> lds_photon(const R *tab, int j, int lane)
 }
 
 // Wave-uniform walk of the top n-MB levels.  `rem` = photons not yet used.
-template <typename R, int N, int MB, int H, int DEPTH>
+template <typename R, int N, int MB, int H, int CL, int DEPTH>
 __device__ __forceinline__ void top_levels(const R *tab, int lane, uint32_t rem, uint32_t cfg0,
-                                           const Chain<R, H> &c, const LMom<R> &q, Acc<H> &acc)
+                                           const LMom<R> &p1, const Chain<R, H> &c,
+                                           const LMom<R> &q, Acc<H> &acc)
 {
     // kept as a loop (not unrolled even where rem is a constant): the walk stays
     // compact and register pressure stays that of one subtree
@@ -241,9 +346,9 @@ __device__ __forceinline__ void top_levels(const R *tab, int lane, uint32_t rem,
                 S.k[s] = lds_photon<R, N>(tab, js, lane);
                 S.v[s] = make_vert<R, H>(S.k[s], cfg0, js);
             }
-            subtree<R, H, MB, (1u << MB) - 1u>(S, cn, qn, acc);
+            run_subtree<R, H, MB, CL>(S, p1, cn, qn, acc);
         } else {
-            top_levels<R, N, MB, H, DEPTH + 1>(tab, lane, rest, cfg0, cn, qn, acc);
+            top_levels<R, N, MB, H, CL, DEPTH + 1>(tab, lane, rest, cfg0, p1, cn, qn, acc);
         }
     }
 }
@@ -253,11 +358,12 @@ template <typename R, int N>
 struct PointIn {
     LMom<R> k[N];   // scaled photon momenta
     LMom<R> q0;     // -p2, scaled
+    LMom<R> p1;     // p1, scaled (pair closing)
 };
 
 // Sum over helicity passes [pass0, pass1) of |ordering sum|^2 (scaled units,
 // without the external normalisations).  Each pass covers H configurations.
-template <typename R, int N, int MB, int H>
+template <typename R, int N, int MB, int H, int CL>
 __device__ __forceinline__ double tree_sum(const PointIn<R, N> &in, R *tab, int lane, int pass0,
                                            int pass1)
 {
@@ -285,9 +391,9 @@ __device__ __forceinline__ double tree_sum(const PointIn<R, N> &in, R *tab, int 
                 S.k[s] = in.k[s];
                 S.v[s] = make_vert<R, H>(in.k[s], cfg0, s);
             }
-            subtree<R, H, N, (1u << N) - 1u>(S, c0, in.q0, acc);
+            run_subtree<R, H, N, CL>(S, in.p1, c0, in.q0, acc);
         } else {
-            top_levels<R, N, MB, H, 0>(tab, lane, (1u << N) - 1u, cfg0, c0, in.q0, acc);
+            top_levels<R, N, MB, H, CL, 0>(tab, lane, (1u << N) - 1u, cfg0, in.p1, c0, in.q0, acc);
         }
 #pragma unroll
         for (int h = 0; h < H; ++h) total += acc.re[h] * acc.re[h] + acc.im[h] * acc.im[h];

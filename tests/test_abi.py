@@ -78,13 +78,40 @@ def test_empty_calls_need_no_device():
     assert H.xsec(4, H.Config(npoints=0))["n_gen"] == 0
 
 
-def test_flop_count_matches_tree_size():
-    """flops/point grows with the tree: nodes sum_{j<n} n!/(n-j)! per helicity."""
+def _flops_unshared(n, mb, h, cl):
+    """Closed form of the algorithmic count when no value is shared between the
+    walk's helicities: every node, closing, vertex block and pair vector h times."""
     import math
+    f = math.factorial
+    ns = min(n, mb)
+    nodes = sum(f(n) // f(n - j) for j in range(1, n - cl + 1))
+    subtrees = f(n) // f(ns)
+    top = sum(f(n) // f(n - j) for j in range(1, n - ns + 1))
+    walk = nodes * (14 + 40 * h) + (ns * subtrees + top) * (3 + 4 * h) + 4 * h
+    if cl == 1:
+        walk += f(n) * 12 * h
+    else:
+        walk += f(n) // 2 * 16 * h
+        walk += subtrees * (ns * (12 + 14 * h) + ns * (ns - 1) * 20 * h + ns * (ns - 1) // 2 * 4 * h)
+    return walk * 2 ** n // h
+
+
+def test_flop_count_of_every_shape():
+    """heget_me2_flops equals the closed form where nothing is shared (h = 1, or
+    photons in run-time slots), and is below it where helicities share values."""
     import paper_0908_4403_amd as H
     for n in range(2, 9):
-        f, mb, h = H.me2_flops(n, H.FP32)
-        nodes = sum(math.factorial(n) // math.factorial(n - j) for j in range(1, n))
-        walks = 2 ** n // h
-        lo = walks * nodes * (14 + 40 * h)
-        assert lo < f < 1.5 * lo
+        for prec in (H.FP32, H.FP64):
+            try:
+                for shape in H.kernel_shapes(n, prec):
+                    H.set_kernel_shape(n, prec, shape)
+                    f, got = H.me2_flops(n, prec)
+                    assert got == shape
+                    mb, h, cl, wpb = shape
+                    ref = _flops_unshared(n, mb, h, cl)
+                    if h == 1 or n > mb:
+                        assert f == ref, (n, shape, f, ref)
+                    else:
+                        assert 0.25 * ref < f < ref, (n, shape, f, ref)
+            finally:
+                H.set_kernel_shape(n, prec, None)

@@ -80,17 +80,25 @@ def test_xsec_against_stored_oracle(H, fname):
         assert abs(got["err_fb"] / g["err_fb"] - 1) < 1e-4
 
 
-def test_mixed_batch_against_stored_oracle(H):
+@pytest.mark.parametrize("schedule", ["BATCH_AUTO", "BATCH_PERSISTENT", "BATCH_BRANCHES"])
+def test_mixed_batch_against_stored_oracle(H, schedule):
     gs = [read_xsec(f) for f in sorted(os.listdir(GOLDEN)) if f.startswith("xsec_mixed_n")]
     assert len(gs) == 6
     ns = [int(g["n"]) for g in gs]
-    for prec, tol in (("FP64", 1e-10), ("FP32", 1e-5)):
-        res = H.xsec_batch(ns, [h_config(H, g, getattr(H, prec)) for g in gs])
-        again = H.xsec_batch(ns, [h_config(H, g, getattr(H, prec)) for g in gs])  # graph replay
-        assert res == again
-        for g, r in zip(gs, res):
-            assert r["n_acc"] == g["n_acc"], (g["n"], r)
-            assert abs(r["sigma_fb"] / g["sigma_fb"] - 1) < tol, (g["n"], prec, r["sigma_fb"], g["sigma_fb"])
+    H.set_batch_schedule(getattr(H, schedule))
+    try:
+        for prec, tol in (("FP64", 1e-10), ("FP32", 1e-5)):
+            cfgs = [h_config(H, g, getattr(H, prec)) for g in gs]
+            res = H.xsec_batch(ns, cfgs)
+            again = H.xsec_batch(ns, cfgs)  # graph replay
+            assert res == again
+            used = H.batch_schedule_in_use(ns, cfgs)
+            assert used in (1, 2) and (schedule == "BATCH_AUTO" or used == getattr(H, schedule))
+            for g, r in zip(gs, res):
+                assert r["n_acc"] == g["n_acc"], (g["n"], r)
+                assert abs(r["sigma_fb"] / g["sigma_fb"] - 1) < tol, (g["n"], prec, r["sigma_fb"], g["sigma_fb"])
+    finally:
+        H.set_batch_schedule(H.BATCH_AUTO)
 
 
 def _full_size_sampled(H, orc, wl, prec, nsample, subsets):
@@ -149,11 +157,12 @@ def test_full_size_pp_5a_properties(H):
     assert a32 == b32
     assert a32["n_acc"] == a64["n_acc"] == c32["n_acc"]
     assert abs(a32["sigma_fb"] / a64["sigma_fb"] - 1) < 1e-5
-    assert abs(c32["sigma_fb"] / a32["sigma_fb"] - 1) < 1e-12
+    assert abs(c32["sigma_fb"] / a32["sigma_fb"] - 1) < 1e-5
 
 
 def test_full_size_mixed_batch_vs_single(H):
-    """The mixed n = 2..7 workload in one batch equals one call per n."""
+    """The mixed n = 2..7 workload in one batch equals one call per n (same
+    points; the batch may run other kernel shapes, so FP32 agrees to the FP32 bar)."""
     from paper_0908_4403_amd.workloads import MIXED_BATCH
     cfgs = [H.Config(mode=s["mode"], prec=H.FP32, seed=s["seed"], npoints=s["npoints"],
                      sqrt_shat_lo=s["lo"], sqrt_shat_hi=s["hi"], pt_min=s["cuts"][0],
@@ -163,4 +172,4 @@ def test_full_size_mixed_batch_vs_single(H):
     for n, c, b in zip(ns, cfgs, batch):
         single = H.xsec(n, c)
         assert single["n_acc"] == b["n_acc"]
-        assert abs(single["sigma_fb"] / b["sigma_fb"] - 1) < 1e-12, (n, single, b)
+        assert abs(single["sigma_fb"] / b["sigma_fb"] - 1) < 1e-5, (n, single, b)

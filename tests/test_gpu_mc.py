@@ -117,3 +117,15 @@ def test_xsec_deterministic_and_empty(H):
     assert a == b
     z = H.xsec(4, H.Config(prec=H.FP32, npoints=0, sqrt_s=1000.0))
     assert z["n_gen"] == 0 and z["sigma_fb"] == 0.0
+
+
+def test_xsec_device_and_async_match_sync(H):
+    import torch
+    cfg = H.Config(prec=H.FP32, seed=8, npoints=20000 + 11, sqrt_s=1000.0)
+    ref = H.xsec(4, cfg)
+    buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    H.xsec_device(4, cfg, buf)
+    h = H.XsecAsync(4, cfg)
+    torch.cuda.synchronize()
+    assert H.result_from_bytes(buf.cpu().numpy()) == ref
+    assert h.result() == ref

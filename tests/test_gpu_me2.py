@@ -140,11 +140,11 @@ def test_autotune_picks_a_compiled_shape(H, orc, tmp_path, monkeypatch):
     cache = tmp_path / "tune.jsonl"
     monkeypatch.setenv("HEGET_TUNING_CACHE", str(cache))
     r = H.autotune(5, H.FP32, 16384)
-    shape = (r["unrolled"], r["helicities_per_walk"], r["waves_per_block"])
+    shape = tuple(r[k] for k in H.SHAPE_FIELDS)
     assert shape == H.kernel_shapes(5, H.FP32)[0]
     assert r["ms"] > 0
     line = cache.read_text().strip()
-    assert f'"n": 5, "mb": {shape[0]}, "h": {shape[1]}, "wpb": {shape[2]}' in line
+    assert f'"n": 5, "mb": {shape[0]}, "h": {shape[1]}, "cl": {shape[2]}, "wpb": {shape[3]}' in line
     ev = cut_events(orc, 5, 1000.0, 17, 100)
     ref, _ = orc.me2_batch(ev)
     assert np.median(np.abs(H.me2(ev, H.FP32) / ref - 1)) <= 1e-5
