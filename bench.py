@@ -45,22 +45,29 @@ def _workloads():
 
 def run_steps(H, torch, n, cfg, steps, warmup):
     """Enqueue `steps` full passes back to back on the current stream; each writes
-    its result record into its own slot of a device buffer (no host callback)."""
-    buf = torch.zeros((warmup + steps, 64), dtype=torch.uint8, device="cuda")
+    its result record into its own slot of a device buffer (no host callback).
+    The step time is taken without per-kernel events (an event record stalls
+    the stream by a few microseconds); the amplitude kernel is then timed over
+    as many further passes with HIP events on the launch stream."""
+    total = warmup + 2 * steps
+    buf = torch.zeros((total, 64), dtype=torch.uint8, device="cuda")
     for k in range(warmup):
         H.xsec_device(n, cfg, buf[k])
     torch.cuda.synchronize()
-    H.timing_enable(True)
-    H.timing_read(reset=True)
     t0 = time.perf_counter()
     for k in range(warmup, warmup + steps):
         H.xsec_device(n, cfg, buf[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    H.timing_enable(True)
+    H.timing_read(reset=True)
+    for k in range(warmup + steps, total):
+        H.xsec_device(n, cfg, buf[k])
+    torch.cuda.synchronize()
     me2_ms, launches = H.timing_read(reset=True)
     H.timing_enable(False)
     host = buf.cpu().numpy()
-    res = [H.result_from_bytes(host[k]) for k in range(warmup + steps)]
+    res = [H.result_from_bytes(host[k]) for k in range(total)]
     assert all(r == res[0] for r in res), "steps disagree"
     return (t1 - t0) * 1e3 / steps, me2_ms / max(launches, 1), launches, res[0]
 
@@ -135,6 +142,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed n=2..7 batch")
     ap.add_argument("--no-tune", action="store_true", help="use the untuned kernel shapes")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (scale for rocprofv3 FETCH/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the |M|^2 path "
@@ -156,6 +165,14 @@ def main():
         for prec, name in ((H.FP32, "fp32"), (H.FP64, "fp64")):
             tuned[name] = H.autotune(n, prec, min(wl["npoints"], 1 << 18))
         print(f"bench: tuned shapes {tuned}", file=sys.stderr, flush=True)
+
+    if args.copy_calibration:
+        from paper_0908_4403_amd.profiling import CALIB_BYTES
+        src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     print(f"bench: {args.workload} FP32 steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
     ms32, k32, l32, r32 = run_steps(H, torch, n, H.Config(prec=H.FP32, **base), args.steps, args.warmup)
@@ -182,6 +199,11 @@ def main():
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(n, wl, args.cpu_seconds)
 
+    kname = f"me2_kernel<float,{n},{shape32[0]},{shape32[1]},{shape32[2]},{shape32[3]}>"
+    from paper_0908_4403_amd.profiling import read_traffic
+    traffic_md = os.path.join(ROOT, "profiles", f"me2_kernel_{args.workload}_hbm_traffic.md")
+    traffic = read_traffic(traffic_md, kname)
+
     line = {
         "metric": "phase-space points/s of helicity-summed |M|^2, n=4..8, FP32-batched vs FP64 plain",
         "value": n_acc / (ms32 * 1e-3),
@@ -201,8 +223,9 @@ def main():
                    "cuts": "pT>%g GeV, |eta|<%g, dR>%g" % tuple(wl["cuts"]), "sigma_fb": r32["sigma_fb"],
                    "sigma_err_fb": r32["err_fb"]},
         "roofline": {"bound": "alu", "achieved": ach32, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach32 / PEAK_VALU_TFLOPS, "traffic": None,
-                     "kernel": f"me2_kernel<float,{n},{shape32[0]},{shape32[1]},{shape32[2]},{shape32[3]}>",
+                     "frac": ach32 / PEAK_VALU_TFLOPS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "kernel": kname,
                      "kernel_ms": k32,
                      "flops_per_point": f32, "frac_of_published_fp32_vector": ach32 / PUBLISHED_FP32_VECTOR_TFLOPS},
         "fp64_plain": {"value": r64["n_acc"] / (ms64 * 1e-3), "ms_per_step": ms64, "kernel_ms": k64,

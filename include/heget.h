@@ -23,7 +23,10 @@
  *     pointer after they return.  Device-pointer calls enqueue work on the
  *     given stream and return; their buffers must stay valid until that work
  *     has completed.  The library owns its device scratch (allocated on first
- *     use, grown as needed, released by heget_shutdown()).
+ *     use, grown as needed, released by heget_shutdown()), one set per
+ *     stream for up to four streams: calls on one stream reuse it in stream
+ *     order with no extra synchronisation; a fifth stream takes over the
+ *     least recently used set after waiting for the device to be idle.
  *   - Calls are serialised by an internal mutex; no exception crosses this
  *     boundary.  On failure the returned status is negative and
  *     heget_last_error() describes it.
@@ -205,7 +208,9 @@ heget_status heget_me2_flops(int n, heget_prec prec, double *flops_per_point, he
 /* Autotuner.  Times every compiled shape of the amplitude kernel for (n,
  * prec) on npoints synthetic points (sqrt(shat) = 1 TeV) generated on the
  * device, and makes the fastest the shape every later call uses for (n,
- * prec) in this process.  If HEGET_TUNING_CACHE names a file, the choice is
+ * prec) in this process (a shape later in the table must be 2% faster than
+ * the best so far to replace it, so near-ties resolve the same way on every
+ * run).  If HEGET_TUNING_CACHE names a file, the choice is
  * also written there (one JSON object per line) and read back by later
  * processes on first device use.  *chosen and *ms (may be NULL) receive the
  * chosen shape and its time per launch.  64 <= npoints < 2^31. */

@@ -5,6 +5,11 @@ in-tree ``libheget.so``; there is no CPU fallback.  Importing this package
 fails loudly if the library has not been built
 (``python paper_0908_4403_amd/build.py``).
 
+The library is opened on the first call, after importing torch when it is
+installed: torch ships its own HIP runtime, and loading it first makes
+libheget bind to that same runtime, so the process has one HIP runtime
+whichever module the caller imported first.
+
 Host-array calls take and return numpy arrays (event layout [npoints, n+2, 4]).
 Device calls take torch tensors on the GPU (SoA layout [(n+2)*4, npoints],
 float64) and enqueue on ``torch.cuda.current_stream()`` unless a stream is
@@ -24,7 +29,6 @@ LIB_PATH = os.path.join(_PKG, "libheget.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_0908_4403_amd/build.py`")
 
-_lib = C.CDLL(LIB_PATH)
 
 OK, WARN_NONFINITE = 0, 1
 ERR_ARG, ERR_RANGE, ERR_ALLOC, ERR_DEVICE = -1, -2, -3, -4
@@ -71,29 +75,55 @@ class Result(C.Structure):
 
 _dp = C.POINTER(C.c_double)
 _st = C.c_int
-_lib.heget_gen_points.argtypes = [C.c_int, C.c_double, C.POINTER(Cuts), C.c_uint64, C.c_int64, _dp, _dp]
-_lib.heget_gen_points_device.argtypes = [C.c_int, C.c_double, C.POINTER(Cuts), C.c_uint64,
-                                         C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
-_lib.heget_me2.argtypes = [C.c_int, C.c_int64, _dp, _dp, C.c_int]
-_lib.heget_me2_device.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
-_lib.heget_xsec.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result)]
-_lib.heget_xsec_async.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result), C.c_void_p]
-_lib.heget_set_batch_schedule.argtypes = [C.c_int]
-_lib.heget_batch_schedule_in_use.argtypes = [C.POINTER(C.c_int), C.POINTER(_Config), C.c_int,
-                                             C.POINTER(C.c_int)]
-_lib.heget_xsec_device.argtypes = [C.c_int, C.POINTER(_Config), C.c_void_p, C.c_void_p]
-_lib.heget_xsec_batch.argtypes = [C.POINTER(C.c_int), C.POINTER(_Config), C.c_int, C.POINTER(Result)]
-_lib.heget_set_couplings.argtypes = [C.c_double, C.c_double]
-_lib.heget_timing_enable.argtypes = [C.c_int]
-_lib.heget_timing_read.argtypes = [_dp, C.POINTER(C.c_int64), C.c_int]
-_lib.heget_me2_flops.argtypes = [C.c_int, C.c_int, _dp, C.POINTER(Shape)]
-_lib.heget_autotune.argtypes = [C.c_int, C.c_int, C.c_int64, C.POINTER(Shape), _dp]
-_lib.heget_kernel_shapes.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(Shape), C.POINTER(C.c_int)]
-_lib.heget_set_kernel_shape.argtypes = [C.c_int, C.c_int, C.POINTER(Shape)]
-_lib.heget_last_error.restype = C.c_char_p
-_lib.heget_shutdown.restype = None
-for _f in EXPORTS[:-2]:
-    getattr(_lib, _f).restype = _st
+_handle = None
+
+
+def _load():
+    global _handle
+    if _handle is not None:
+        return _handle
+    try:
+        import torch  # noqa: F401  (its HIP runtime first; see the module docstring)
+    except ImportError:
+        pass
+    lib = C.CDLL(LIB_PATH)
+    lib.heget_gen_points.argtypes = [C.c_int, C.c_double, C.POINTER(Cuts), C.c_uint64, C.c_int64,
+                                     _dp, _dp]
+    lib.heget_gen_points_device.argtypes = [C.c_int, C.c_double, C.POINTER(Cuts), C.c_uint64,
+                                            C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.heget_me2.argtypes = [C.c_int, C.c_int64, _dp, _dp, C.c_int]
+    lib.heget_me2_device.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_int,
+                                     C.c_void_p]
+    lib.heget_xsec.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result)]
+    lib.heget_xsec_async.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result), C.c_void_p]
+    lib.heget_set_batch_schedule.argtypes = [C.c_int]
+    lib.heget_batch_schedule_in_use.argtypes = [C.POINTER(C.c_int), C.POINTER(_Config), C.c_int,
+                                                C.POINTER(C.c_int)]
+    lib.heget_xsec_device.argtypes = [C.c_int, C.POINTER(_Config), C.c_void_p, C.c_void_p]
+    lib.heget_xsec_batch.argtypes = [C.POINTER(C.c_int), C.POINTER(_Config), C.c_int,
+                                     C.POINTER(Result)]
+    lib.heget_set_couplings.argtypes = [C.c_double, C.c_double]
+    lib.heget_timing_enable.argtypes = [C.c_int]
+    lib.heget_timing_read.argtypes = [_dp, C.POINTER(C.c_int64), C.c_int]
+    lib.heget_me2_flops.argtypes = [C.c_int, C.c_int, _dp, C.POINTER(Shape)]
+    lib.heget_autotune.argtypes = [C.c_int, C.c_int, C.c_int64, C.POINTER(Shape), _dp]
+    lib.heget_kernel_shapes.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(Shape),
+                                        C.POINTER(C.c_int)]
+    lib.heget_set_kernel_shape.argtypes = [C.c_int, C.c_int, C.POINTER(Shape)]
+    lib.heget_last_error.restype = C.c_char_p
+    lib.heget_shutdown.restype = None
+    for f in EXPORTS[:-2]:
+        getattr(lib, f).restype = _st
+    _handle = lib
+    return lib
+
+
+class _LazyLib:
+    def __getattr__(self, name):
+        return getattr(_load(), name)
+
+
+_lib = _LazyLib()
 
 
 class HegetError(RuntimeError):

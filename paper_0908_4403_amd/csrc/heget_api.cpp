@@ -50,13 +50,25 @@ heget_status fail(heget_status s, const std::string &msg)
 
 // ---------------------------------------------------------------- device state
 
+// Scratch memory of one stream.  Work on one stream is ordered, so calls on
+// the same stream reuse their buffers with no synchronisation; each stream
+// has its own set, so calls on different streams never share scratch.
+constexpr int kContexts = 4;
+struct Scratch {
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    uint64_t last_use = 0;
+    std::vector<void *> buf;  // one per Slot
+    std::vector<size_t> cap;
+};
+
 struct State {
     bool ready = false;
     int device = -1;
     hipStream_t stream = nullptr;     // library stream for the synchronous calls
-    hipEvent_t ws_free = nullptr;     // recorded after every use of the scratch
-    std::vector<void *> buf;          // scratch slots
-    std::vector<size_t> cap;
+    Scratch ctx[kContexts];           // ctx[0] belongs to `stream`
+    Scratch *cur = nullptr;           // context of the call in progress
+    uint64_t tick = 0;
     double *pinned = nullptr;         // staging ring for results (kRing slots of 8 doubles)
     std::atomic<unsigned> ring{0};
     // side streams and fork/join events of the parallel batch schedule
@@ -74,8 +86,8 @@ State g;
 constexpr int kRing = 256;
 
 enum Slot {
-    S_MOM, S_WFAC, S_FLAG, S_BCOUNT, S_OFFS, S_COUNT, S_INDEX, S_PART, S_ME2, S_PARTIALS, S_RES,
-    S_FLAGS, S_OUT, S_BATCH, S_NSLOTS
+    S_MOM, S_WFAC, S_FLAG, S_BCOUNT, S_OFFS, S_COUNT, S_INDEX, S_PART, S_PARTIALS, S_RES, S_FLAGS,
+    S_OUT, S_BATCH, S_NSLOTS
 };
 
 // Captured mixed-n batches, keyed by their configuration; replayed on repeat calls.
@@ -107,14 +119,20 @@ heget_status ensure_device()
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev <= 0)
-        return fail(HEGET_ERR_DEVICE, "no HIP device available");
+        return fail(HEGET_ERR_DEVICE, std::string("no HIP device available (hipGetDeviceCount: ") +
+                                          hipGetErrorString(e) + ", " + std::to_string(ndev) +
+                                          " devices)");
     HG_HIP(hipGetDevice(&g.device));
     HG_HIP(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking));
-    HG_HIP(hipEventCreateWithFlags(&g.ws_free, hipEventDisableTiming));
     HG_HIP(hipHostMalloc(reinterpret_cast<void **>(&g.pinned), sizeof(double) * 8 * kRing,
                          hipHostMallocDefault));
-    g.buf.assign(S_NSLOTS, nullptr);
-    g.cap.assign(S_NSLOTS, 0);
+    for (Scratch &c : g.ctx) {
+        c.buf.assign(S_NSLOTS, nullptr);
+        c.cap.assign(S_NSLOTS, 0);
+        c.bound = false;
+    }
+    g.ctx[0].stream = g.stream;
+    g.ctx[0].bound = true;
     hipDeviceProp_t prop;
     HG_HIP(hipGetDeviceProperties(&prop, g.device));
     g_arch = prop.gcnArchName;
@@ -124,21 +142,50 @@ heget_status ensure_device()
     return HEGET_OK;
 }
 
-// Scratch slot of at least `bytes`; grows (after the device is idle) when short.
+// Make the scratch set of stream s current (call before scratch()).  A stream
+// seen for the first time takes a free set, else the least recently used set
+// of another user stream once the device is idle (context 0 stays with the
+// library stream, whose set also holds the captured batch graphs' memory).
+heget_status scratch_bind(hipStream_t s)
+{
+    Scratch *hit = nullptr;
+    for (Scratch &c : g.ctx)
+        if (c.bound && c.stream == s) hit = &c;
+    if (!hit) {
+        for (int i = 1; i < kContexts && !hit; ++i)
+            if (!g.ctx[i].bound) hit = &g.ctx[i];
+        if (!hit) {
+            hit = &g.ctx[1];
+            for (int i = 2; i < kContexts; ++i)
+                if (g.ctx[i].last_use < hit->last_use) hit = &g.ctx[i];
+            HG_HIP(hipDeviceSynchronize());  // its buffers may still be in use on the old stream
+        }
+        hit->stream = s;
+        hit->bound = true;
+    }
+    hit->last_use = ++g.tick;
+    g.cur = hit;
+    return HEGET_OK;
+}
+
+// Slot of the current scratch set with at least `bytes`; grows (after the
+// device is idle) when short.
 heget_status scratch(int slot, size_t bytes, void **out)
 {
+    if (!g.cur) return fail(HEGET_ERR_DEVICE, "internal: scratch used before scratch_bind");
+    Scratch &c = *g.cur;
     bytes = bytes < 256 ? 256 : bytes;
-    if (g.cap[slot] < bytes) {
+    if (c.cap[slot] < bytes) {
         HG_HIP(hipDeviceSynchronize());
         if (slot == S_BATCH) drop_graphs();
-        if (g.buf[slot]) HG_HIP(hipFree(g.buf[slot]));
-        g.buf[slot] = nullptr;
-        g.cap[slot] = 0;
+        if (c.buf[slot]) HG_HIP(hipFree(c.buf[slot]));
+        c.buf[slot] = nullptr;
+        c.cap[slot] = 0;
         size_t want = bytes + bytes / 4;
-        HG_HIP(hipMalloc(&g.buf[slot], want));
-        g.cap[slot] = want;
+        HG_HIP(hipMalloc(&c.buf[slot], want));
+        c.cap[slot] = want;
     }
-    *out = g.buf[slot];
+    *out = c.buf[slot];
     return HEGET_OK;
 }
 
@@ -148,19 +195,6 @@ heget_status scratch_t(int slot, size_t count, T **out)
     void *p = nullptr;
     HG_TRY(scratch(slot, count * sizeof(T), &p));
     *out = static_cast<T *>(p);
-    return HEGET_OK;
-}
-
-// Scratch users on different streams are ordered through one event.
-heget_status scratch_acquire(hipStream_t s)
-{
-    HG_HIP(hipStreamWaitEvent(s, g.ws_free, 0));
-    return HEGET_OK;
-}
-
-heget_status scratch_release(hipStream_t s)
-{
-    HG_HIP(hipEventRecord(g.ws_free, s));
     return HEGET_OK;
 }
 
@@ -458,10 +492,11 @@ heget_status me2_on_device(int n, int64_t np, const double *d_mom, double *d_out
     double *part = d_out;
     if (nchunks > 1) HG_TRY(scratch_t<double>(S_PART, size_t(nchunks) * size_t(np), &part));
     heget::Me2Args a{d_mom, np, nullptr, nullptr, np, nchunks, me2_coef(n, g_alpha, g_charge),
-                     part, np, d_flags};
+                     part, np, nullptr, nullptr, d_flags};
     HG_TRY(launch_me2_timed(*v, a, s));
     if (nchunks > 1)
-        HG_HIP(heget::launch_sum_chunks(part, nchunks, np, nullptr, np, d_out, d_flags, s));
+        HG_HIP(heget::launch_sum_chunks(part, nchunks, np, nullptr, np, d_out, nullptr, nullptr,
+                                        nullptr, d_flags, s));
     return HEGET_OK;
 }
 
@@ -508,71 +543,113 @@ void xsec_finish(void *p)
     delete t;
 }
 
+// Device buffers of one Monte-Carlo configuration.
+struct McBufs {
+    double *mom, *wfac, *part, *partials, *res;
+    uint8_t *flag;
+    int32_t *bcount, *offs, *index;
+    int64_t *d_count;
+    int nchunks;
+};
+
+// Status of a finished Monte-Carlo call from its device flags.
+heget_status mc_flags_status(unsigned flags)
+{
+    if (flags & 1u) {
+        g_err = "some weights were not finite";
+        return HEGET_WARN_NONFINITE;
+    }
+    return HEGET_OK;
+}
+
+heget::GenParams slice_gen_params(int n, const heget_config &c)
+{
+    heget::GenParams gp{};
+    gp.mode = c.mode;
+    gp.seed = c.seed;
+    gp.npoints = c.npoints;
+    gp.sqrt_s = c.sqrt_s;
+    gp.lo = c.sqrt_shat_lo;
+    gp.hi = c.sqrt_shat_hi;
+    gp.pt_min = c.cuts.pt_min;
+    gp.eta_max = c.cuts.eta_max;
+    gp.dr_min = c.cuts.dr_min;
+    gp.partonic_coef = partonic_coef(n);
+    gp.phase_volume_coef = phase_volume_coef(n);
+    gp.weight_kind = 1;
+    return gp;
+}
+
+// Generation and compaction: every point's momenta and weight factor, the
+// survivor list (point order) and the survivor count in *d_count; `clear`
+// (optional) is zeroed by the generation launch.
+heget_status enqueue_generation(int n, const heget_config &c, const McBufs &b, hipStream_t s,
+                                unsigned *clear = nullptr)
+{
+    const int64_t np = c.npoints;
+    heget::GenParams gp = slice_gen_params(n, c);
+    gp.clear_word = clear;
+    HG_HIP(heget::launch_gen(n, gp, b.mom, np, b.wfac, b.flag, b.bcount, s));
+    HG_HIP(heget::launch_scan(b.bcount, static_cast<int>((np + 255) / 256), b.offs, b.d_count, s));
+    HG_HIP(heget::launch_compact(b.flag, np, b.offs, b.index, s));
+    return HEGET_OK;
+}
+
+// Weighted sums after the amplitude pass: the weighted chunk sums when the
+// amplitude pass wrote |M|^2 (split walks, or `weighted_in_me2` false), then
+// the fixed-order reduction into b.res (and the result record if given).
+heget_status enqueue_reduction(const heget_config &c, const McBufs &b, unsigned *flags, void *record,
+                               hipStream_t s, bool weighted_in_me2 = true)
+{
+    const int64_t np = c.npoints;
+    if (b.nchunks > 1 || !weighted_in_me2)
+        HG_HIP(heget::launch_sum_chunks(b.part, b.nchunks, np, b.d_count, np, nullptr, b.index,
+                                        b.wfac, b.partials, flags, s));
+    HG_HIP(heget::launch_final(b.partials, b.d_count, np, b.res, record, s));
+    return HEGET_OK;
+}
+
+heget::Me2Args mc_me2_args(int n, const heget_config &c, const McBufs &b, unsigned *flags)
+{
+    return heget::Me2Args{b.mom, c.npoints, b.index, b.d_count, c.npoints, b.nchunks,
+                          me2_coef(n, c.alpha, c.charge), b.part, c.npoints, b.wfac,
+                          b.nchunks == 1 ? b.partials : nullptr, flags};
+}
+
 // Enqueue the whole path.  The result goes to d_out (device-writable, filled by
 // a kernel) when given, else to *out through the pinned ring and a host callback.
 heget_status xsec_enqueue(int n, const heget_config *cfg, heget_result *out, heget_result *d_out,
                           hipStream_t s, unsigned **flags_out)
 {
     const int64_t np = cfg->npoints;
-    const int nb = static_cast<int>((np + 255) / 256);
     const heget::Me2Variant *v = pick_variant(cfg->prec, n);
     if (!v) return fail(HEGET_ERR_ARG, "no compiled amplitude kernel for this n/precision");
-    const int nchunks = plan_chunks(*v, np / 2);
 
-    double *mom, *wfac, *part, *me2, *partials, *res;
-    uint8_t *flag;
-    int32_t *bcount, *offs, *index;
-    int64_t *d_count;
+    const int64_t nb = (np + 255) / 256;
+    McBufs b{};
+    b.nchunks = plan_chunks(*v, np / 2);
     unsigned *flags;
-    HG_TRY(scratch_t<double>(S_MOM, size_t(n + 2) * 4 * size_t(np), &mom));
-    HG_TRY(scratch_t<double>(S_WFAC, size_t(np), &wfac));
-    HG_TRY(scratch_t<uint8_t>(S_FLAG, size_t(np), &flag));
-    HG_TRY(scratch_t<int32_t>(S_BCOUNT, size_t(nb), &bcount));
-    HG_TRY(scratch_t<int32_t>(S_OFFS, size_t(nb), &offs));
-    HG_TRY(scratch_t<int64_t>(S_COUNT, 1, &d_count));
-    HG_TRY(scratch_t<int32_t>(S_INDEX, size_t(np), &index));
-    HG_TRY(scratch_t<double>(S_PART, size_t(nchunks) * size_t(np), &part));
-    me2 = part;
-    if (nchunks > 1) HG_TRY(scratch_t<double>(S_ME2, size_t(np), &me2));
-    HG_TRY(scratch_t<double>(S_PARTIALS, size_t(3) * nb, &partials));
-    HG_TRY(scratch_t<double>(S_RES, 8, &res));
+    HG_TRY(scratch_bind(s));
+    HG_TRY(scratch_t<double>(S_MOM, size_t(n + 2) * 4 * size_t(np), &b.mom));
+    HG_TRY(scratch_t<double>(S_WFAC, size_t(np), &b.wfac));
+    HG_TRY(scratch_t<uint8_t>(S_FLAG, size_t(np), &b.flag));
+    HG_TRY(scratch_t<int32_t>(S_BCOUNT, size_t(nb), &b.bcount));
+    HG_TRY(scratch_t<int32_t>(S_OFFS, size_t(nb), &b.offs));
+    HG_TRY(scratch_t<int64_t>(S_COUNT, 1, &b.d_count));
+    HG_TRY(scratch_t<int32_t>(S_INDEX, size_t(np), &b.index));
+    b.part = nullptr;
+    if (b.nchunks > 1) HG_TRY(scratch_t<double>(S_PART, size_t(b.nchunks) * size_t(np), &b.part));
+    HG_TRY(scratch_t<double>(S_PARTIALS, size_t(3) * size_t((np + 63) / 64), &b.partials));
+    HG_TRY(scratch_t<double>(S_RES, 8, &b.res));
     HG_TRY(scratch_t<unsigned>(S_FLAGS, 1, &flags));
 
-    heget::GenParams gp{};
-    gp.mode = cfg->mode;
-    gp.seed = cfg->seed;
-    gp.first = 0;
-    gp.npoints = np;
-    gp.sqrt_s = cfg->sqrt_s;
-    gp.lo = cfg->sqrt_shat_lo;
-    gp.hi = cfg->sqrt_shat_hi;
-    gp.pt_min = cfg->cuts.pt_min;
-    gp.eta_max = cfg->cuts.eta_max;
-    gp.dr_min = cfg->cuts.dr_min;
-    gp.partonic_coef = partonic_coef(n);
-    gp.phase_volume_coef = phase_volume_coef(n);
-    gp.weight_kind = 1;
-
-    HG_TRY(scratch_acquire(s));
-    HG_HIP(heget::launch_zero_u32(flags, 1, s));
-    HG_HIP(heget::launch_gen(n, gp, mom, np, wfac, flag, bcount, s));
-    HG_HIP(heget::launch_scan(bcount, nb, offs, d_count, s));
-    HG_HIP(heget::launch_compact(flag, np, offs, index, s));
-    heget::Me2Args a{mom, np, index, d_count, np, nchunks, me2_coef(n, cfg->alpha, cfg->charge),
-                     part, np, flags};
-    HG_TRY(launch_me2_timed(*v, a, s));
-    if (nchunks > 1)
-        HG_HIP(heget::launch_sum_chunks(part, nchunks, np, d_count, np, me2, flags, s));
-    HG_HIP(heget::launch_weights(me2, index, wfac, d_count, np, partials, flags, s));
-    HG_HIP(heget::launch_final(partials, nb, d_count, res, s));
-    if (d_out) {
-        HG_HIP(heget::launch_result(res, np, d_out, s));
-        HG_TRY(scratch_release(s));
-    } else {
+    HG_TRY(enqueue_generation(n, *cfg, b, s, flags));  // also clears flags
+    HG_TRY(launch_me2_timed(*v, mc_me2_args(n, *cfg, b, flags), s));
+    HG_TRY(enqueue_reduction(*cfg, b, flags, d_out, s));
+    if (!d_out) {
         const unsigned slot = g.ring.fetch_add(1) % kRing;
         double *staged = g.pinned + 8 * slot;
-        HG_HIP(hipMemcpyAsync(staged, res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HG_TRY(scratch_release(s));
+        HG_HIP(hipMemcpyAsync(staged, b.res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
         XsecTicket *t = new XsecTicket{out, staged, np};
         HG_HIP(hipLaunchHostFunc(s, xsec_finish, t));
     }
@@ -598,11 +675,8 @@ struct Arena {
 };
 
 struct SliceBufs {
-    double *mom, *wfac, *part, *me2, *partials, *res;
-    uint8_t *flag;
-    int32_t *bcount, *offs, *index;
-    int64_t *d_count;
-    int nb, nchunks, mb, h, cl;
+    McBufs b;
+    int mb, h, cl;
 };
 
 void carve_batch(Arena &ar, int ncfg, const int *n, const heget_config *cfgs, int schedule,
@@ -613,47 +687,30 @@ void carve_batch(Arena &ar, int ncfg, const int *n, const heget_config *cfgs, in
     *item_start = ar.take<int64_t>(heget::kMaxSlices + 1);
     for (int s = 0; s < ncfg; ++s) {
         const int64_t np = cfgs[s].npoints;
-        SliceBufs &b = sb[s];
+        SliceBufs &sl = sb[s];
         if (schedule == 1) {
-            heget::me2_batch_shape(cfgs[s].prec, n[s], &b.mb, &b.h, &b.cl);
+            heget::me2_batch_shape(cfgs[s].prec, n[s], &sl.mb, &sl.h, &sl.cl);
         } else {
             const heget::Me2Variant *v = pick_variant(cfgs[s].prec, n[s]);
-            b.mb = v->mb;
-            b.h = v->h;
-            b.cl = v->cl;
+            sl.mb = v->mb;
+            sl.h = v->h;
+            sl.cl = v->cl;
         }
-        b.nb = static_cast<int>((np + 255) / 256);
-        b.nchunks = plan_chunks_shape(n[s], b.mb, b.h, b.cl, np / 2);
+        McBufs &b = sl.b;
+        b.nchunks = plan_chunks_shape(n[s], sl.mb, sl.h, sl.cl, np / 2);
         b.mom = ar.take<double>(size_t(n[s] + 2) * 4 * size_t(np));
         b.wfac = ar.take<double>(size_t(np));
         b.flag = ar.take<uint8_t>(size_t(np));
-        b.bcount = ar.take<int32_t>(size_t(b.nb));
-        b.offs = ar.take<int32_t>(size_t(b.nb));
-        b.d_count = ar.take<int64_t>(1);
+        b.bcount = ar.take<int32_t>(size_t((np + 255) / 256));
+        b.offs = ar.take<int32_t>(size_t((np + 255) / 256));
         b.index = ar.take<int32_t>(size_t(np));
-        b.part = ar.take<double>(size_t(b.nchunks) * size_t(np));
-        b.me2 = b.nchunks > 1 ? ar.take<double>(size_t(np)) : b.part;
-        b.partials = ar.take<double>(size_t(3) * b.nb);
+        b.d_count = ar.take<int64_t>(1);
+        // the persistent kernel always writes |M|^2 per chunk
+        const bool need_part = b.nchunks > 1 || schedule == 1;
+        b.part = need_part ? ar.take<double>(size_t(b.nchunks) * size_t(np)) : nullptr;
+        b.partials = ar.take<double>(size_t(3) * size_t((np + 63) / 64));
         b.res = ar.take<double>(4);
     }
-}
-
-heget::GenParams slice_gen_params(int n, const heget_config &c)
-{
-    heget::GenParams gp{};
-    gp.mode = c.mode;
-    gp.seed = c.seed;
-    gp.npoints = c.npoints;
-    gp.sqrt_s = c.sqrt_s;
-    gp.lo = c.sqrt_shat_lo;
-    gp.hi = c.sqrt_shat_hi;
-    gp.pt_min = c.cuts.pt_min;
-    gp.eta_max = c.cuts.eta_max;
-    gp.dr_min = c.cuts.dr_min;
-    gp.partonic_coef = partonic_coef(n);
-    gp.phase_volume_coef = phase_volume_coef(n);
-    gp.weight_kind = 1;
-    return gp;
 }
 
 // Parallel schedule: one fork/join branch per configuration on the side
@@ -666,20 +723,11 @@ heget_status batch_enqueue_branches(int ncfg, const int *n, const heget_config *
     for (int i = 0; i < ncfg; ++i) {
         hipStream_t si = g.side[i];
         const heget_config &c = cfgs[i];
-        SliceBufs &b = sb[i];
-        const int64_t np = c.npoints;
+        const McBufs &b = sb[i].b;
         HG_HIP(hipStreamWaitEvent(si, g.fork, 0));
-        HG_HIP(heget::launch_gen(n[i], slice_gen_params(n[i], c), b.mom, np, b.wfac, b.flag, b.bcount, si));
-        HG_HIP(heget::launch_scan(b.bcount, b.nb, b.offs, b.d_count, si));
-        HG_HIP(heget::launch_compact(b.flag, np, b.offs, b.index, si));
-        const heget::Me2Variant *v = pick_variant(c.prec, n[i]);
-        heget::Me2Args ma{b.mom, np, b.index, b.d_count, np, b.nchunks,
-                          me2_coef(n[i], c.alpha, c.charge), b.part, np, flags};
-        HG_HIP(heget::launch_me2(*v, ma, si));
-        if (b.nchunks > 1)
-            HG_HIP(heget::launch_sum_chunks(b.part, b.nchunks, np, b.d_count, np, b.me2, flags, si));
-        HG_HIP(heget::launch_weights(b.me2, b.index, b.wfac, b.d_count, np, b.partials, flags, si));
-        HG_HIP(heget::launch_final(b.partials, b.nb, b.d_count, b.res, si));
+        HG_TRY(enqueue_generation(n[i], c, b, si));
+        HG_HIP(heget::launch_me2(*pick_variant(c.prec, n[i]), mc_me2_args(n[i], c, b, flags), si));
+        HG_TRY(enqueue_reduction(c, b, flags, nullptr, si));
         HG_HIP(hipMemcpyAsync(staged + 4 * i, b.res, 4 * sizeof(double), hipMemcpyDeviceToHost, si));
         HG_HIP(hipEventRecord(g.join[i], si));
         HG_HIP(hipStreamWaitEvent(s, g.join[i], 0));
@@ -695,32 +743,15 @@ heget_status batch_enqueue(int ncfg, const int *n, const heget_config *cfgs, Sli
 {
     HG_HIP(heget::launch_zero_u32(flags, 1, s));
     HG_HIP(heget::launch_zero_u32(reinterpret_cast<unsigned *>(queue), 2, s));
-    for (int i = 0; i < ncfg; ++i) {
-        const heget_config &c = cfgs[i];
-        SliceBufs &b = sb[i];
-        heget::GenParams gp{};
-        gp.mode = c.mode;
-        gp.seed = c.seed;
-        gp.npoints = c.npoints;
-        gp.sqrt_s = c.sqrt_s;
-        gp.lo = c.sqrt_shat_lo;
-        gp.hi = c.sqrt_shat_hi;
-        gp.pt_min = c.cuts.pt_min;
-        gp.eta_max = c.cuts.eta_max;
-        gp.dr_min = c.cuts.dr_min;
-        gp.partonic_coef = partonic_coef(n[i]);
-        gp.phase_volume_coef = phase_volume_coef(n[i]);
-        gp.weight_kind = 1;
-        HG_HIP(heget::launch_gen(n[i], gp, b.mom, c.npoints, b.wfac, b.flag, b.bcount, s));
-        HG_HIP(heget::launch_scan(b.bcount, b.nb, b.offs, b.d_count, s));
-        HG_HIP(heget::launch_compact(b.flag, c.npoints, b.offs, b.index, s));
-    }
+    for (int i = 0; i < ncfg; ++i) HG_TRY(enqueue_generation(n[i], cfgs[i], sb[i].b, s));
     // work items of the most expensive slices first (longest-processing-time order)
     std::vector<int> order(ncfg);
     for (int i = 0; i < ncfg; ++i) order[i] = i;
+    auto cost = [&](int x) {
+        return me2_flops_per_point(n[x], sb[x].mb, sb[x].h, sb[x].cl) / sb[x].b.nchunks;
+    };
     std::sort(order.begin(), order.end(), [&](int x, int y) {
-        const double cx = me2_flops_per_point(n[x], sb[x].mb, sb[x].h, sb[x].cl) / sb[x].nchunks;
-        const double cy = me2_flops_per_point(n[y], sb[y].mb, sb[y].h, sb[y].cl) / sb[y].nchunks;
+        const double cx = cost(x), cy = cost(y);
         return cx > cy || (cx == cy && x < y);
     });
     heget::BatchDesc bd{};
@@ -730,10 +761,9 @@ heget_status batch_enqueue(int ncfg, const int *n, const heget_config *cfgs, Sli
     bd.flags = flags;
     for (int k = 0; k < ncfg; ++k) {
         const int i = order[k];
-        const heget_config &c = cfgs[i];
-        bd.s[k] = heget::SliceDesc{sb[i].mom, c.npoints, sb[i].index, sb[i].d_count, sb[i].part,
-                                   c.npoints, me2_coef(n[i], c.alpha, c.charge), n[i],
-                                   sb[i].nchunks};
+        const heget::Me2Args ma = mc_me2_args(n[i], cfgs[i], sb[i].b, flags);
+        bd.s[k] = heget::SliceDesc{ma.mom, ma.ld, ma.index, ma.d_count, ma.out, ma.ld_out, ma.wfac,
+                                   ma.partials, ma.coef, n[i], ma.nchunks};
     }
     HG_HIP(heget::launch_batch_plan(bd, s));
     int cus = 0;
@@ -741,13 +771,9 @@ heget_status batch_enqueue(int ncfg, const int *n, const heget_config *cfgs, Sli
     const int grid = cus * heget::me2_batch_blocks_per_cu(cfgs[0].prec);
     HG_HIP(heget::launch_me2_batch(cfgs[0].prec, bd, grid, s));
     for (int i = 0; i < ncfg; ++i) {
-        SliceBufs &b = sb[i];
-        const int64_t np = cfgs[i].npoints;
-        if (b.nchunks > 1)
-            HG_HIP(heget::launch_sum_chunks(b.part, b.nchunks, np, b.d_count, np, b.me2, flags, s));
-        HG_HIP(heget::launch_weights(b.me2, b.index, b.wfac, b.d_count, np, b.partials, flags, s));
-        HG_HIP(heget::launch_final(b.partials, b.nb, b.d_count, b.res, s));
-        HG_HIP(hipMemcpyAsync(staged + 4 * i, b.res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HG_TRY(enqueue_reduction(cfgs[i], sb[i].b, flags, nullptr, s, false));
+        HG_HIP(hipMemcpyAsync(staged + 4 * i, sb[i].b.res, 4 * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
     }
     HG_HIP(hipMemcpyAsync(staged + 4 * heget::kMaxSlices, flags, sizeof(unsigned),
                           hipMemcpyDeviceToHost, s));
@@ -854,6 +880,8 @@ heget_status heget_gen_points(int n, double sqrt_s, const heget_cuts *cuts, uint
     HG_TRY(ensure_device());
     double *d_mom, *d_w;
     const size_t rows = size_t(n + 2) * 4;
+    hipStream_t s = g.stream;
+    HG_TRY(scratch_bind(s));
     HG_TRY(scratch_t<double>(S_MOM, rows * size_t(npoints), &d_mom));
     HG_TRY(scratch_t<double>(S_WFAC, size_t(npoints), &d_w));
     heget::GenParams gp{};
@@ -867,13 +895,10 @@ heget_status heget_gen_points(int n, double sqrt_s, const heget_cuts *cuts, uint
     gp.phase_volume_coef = phase_volume_coef(n);
     gp.partonic_coef = partonic_coef(n);
     gp.weight_kind = 0;
-    hipStream_t s = g.stream;
-    HG_TRY(scratch_acquire(s));
     HG_HIP(heget::launch_gen(n, gp, d_mom, npoints, d_w, nullptr, nullptr, s));
     std::vector<double> soa(rows * size_t(npoints));
     HG_HIP(hipMemcpyAsync(soa.data(), d_mom, soa.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HG_HIP(hipMemcpyAsync(weight, d_w, size_t(npoints) * sizeof(double), hipMemcpyDeviceToHost, s));
-    HG_TRY(scratch_release(s));
     HG_HIP(hipStreamSynchronize(s));
     for (int64_t i = 0; i < npoints; ++i)
         for (size_t r = 0; r < rows; ++r) momenta[size_t(i) * rows + r] = soa[r * size_t(npoints) + size_t(i)];
@@ -928,18 +953,17 @@ heget_status heget_me2(int n, int64_t npoints, const double *momenta, double *ou
         for (size_t r = 0; r < rows; ++r) soa[r * size_t(npoints) + size_t(i)] = momenta[size_t(i) * rows + r];
     double *d_mom, *d_out;
     unsigned *d_flags;
+    hipStream_t s = g.stream;
+    HG_TRY(scratch_bind(s));
     HG_TRY(scratch_t<double>(S_MOM, soa.size(), &d_mom));
     HG_TRY(scratch_t<double>(S_OUT, size_t(npoints), &d_out));
     HG_TRY(scratch_t<unsigned>(S_FLAGS, 1, &d_flags));
-    hipStream_t s = g.stream;
-    HG_TRY(scratch_acquire(s));
     HG_HIP(hipMemcpyAsync(d_mom, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice, s));
     HG_HIP(heget::launch_zero_u32(d_flags, 1, s));
     HG_TRY(me2_on_device(n, npoints, d_mom, d_out, prec, s, d_flags));
     unsigned flags = 0;
     HG_HIP(hipMemcpyAsync(out_me2, d_out, size_t(npoints) * sizeof(double), hipMemcpyDeviceToHost, s));
     HG_HIP(hipMemcpyAsync(&flags, d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-    HG_TRY(scratch_release(s));
     HG_HIP(hipStreamSynchronize(s));
     if (flags & 1u) {
         g_err = "some points gave a non-finite |M|^2 (check the preconditions)";
@@ -961,10 +985,9 @@ heget_status heget_me2_device(int n, int64_t npoints, const double *d_mom, doubl
     HG_TRY(ensure_device());
     hipStream_t s = static_cast<hipStream_t>(stream);
     unsigned *d_flags;
+    HG_TRY(scratch_bind(s));
     HG_TRY(scratch_t<unsigned>(S_FLAGS, 1, &d_flags));
-    HG_TRY(scratch_acquire(s));
     HG_TRY(me2_on_device(n, npoints, d_mom, d_out, prec, s, d_flags));
-    HG_TRY(scratch_release(s));
     return HEGET_OK;
 }
 
@@ -1011,11 +1034,7 @@ heget_status heget_xsec(int n, const heget_config *cfg, heget_result *out)
     unsigned flags = 0;
     HG_HIP(hipMemcpyAsync(&flags, d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, g.stream));
     HG_HIP(hipStreamSynchronize(g.stream));
-    if (flags & 1u) {
-        g_err = "some weights were not finite";
-        return HEGET_WARN_NONFINITE;
-    }
-    return HEGET_OK;
+    return mc_flags_status(flags);
 }
 
 heget_status heget_set_batch_schedule(int schedule)
@@ -1054,7 +1073,7 @@ heget_status heget_xsec_batch(const int *n, const heget_config *cfgs, int ncfg,
     BatchGraph *bg = nullptr;
     for (BatchGraph &b : g_graphs)
         if (b.key == key) bg = &b;
-    HG_TRY(scratch_acquire(s));
+    HG_TRY(scratch_bind(s));
     if (!bg) {
         if (g_graphs.size() >= 8) drop_graphs();
         BatchGraph nb;
@@ -1082,16 +1101,11 @@ heget_status heget_xsec_batch(const int *n, const heget_config *cfgs, int ncfg,
         bg = &g_graphs.back();
     }
     HG_HIP(hipGraphLaunch(bg->exec, s));
-    HG_TRY(scratch_release(s));
     HG_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < ncfg; ++i) out[i] = make_result(bg->staged + 4 * i, cfgs[i].npoints);
     unsigned fl = 0;
     std::memcpy(&fl, bg->staged + 4 * heget::kMaxSlices, sizeof(unsigned));
-    if (fl & 1u) {
-        g_err = "some weights were not finite";
-        return HEGET_WARN_NONFINITE;
-    }
-    return HEGET_OK;
+    return mc_flags_status(fl);
 }
 
 heget_status heget_batch_schedule_in_use(const int *n, const heget_config *cfgs,
@@ -1121,6 +1135,7 @@ heget_status heget_autotune(int n, heget_prec prec, int64_t npoints, heget_shape
     hipStream_t s = g.stream;
     double *d_mom, *d_w, *d_out;
     unsigned *d_flags;
+    HG_TRY(scratch_bind(s));
     HG_TRY(scratch_t<double>(S_MOM, size_t(n + 2) * 4 * size_t(npoints), &d_mom));
     HG_TRY(scratch_t<double>(S_WFAC, size_t(npoints), &d_w));
     HG_TRY(scratch_t<unsigned>(S_FLAGS, 1, &d_flags));
@@ -1136,7 +1151,6 @@ heget_status heget_autotune(int n, heget_prec prec, int64_t npoints, heget_shape
     gp.dr_min = 0.4;
     gp.phase_volume_coef = phase_volume_coef(n);
     gp.weight_kind = 0;
-    HG_TRY(scratch_acquire(s));
     HG_HIP(heget::launch_gen(n, gp, d_mom, npoints, d_w, nullptr, nullptr, s));
     HG_HIP(heget::launch_zero_u32(d_flags, 1, s));
     hipEvent_t e0, e1;
@@ -1153,7 +1167,7 @@ heget_status heget_autotune(int n, heget_prec prec, int64_t npoints, heget_shape
         double *out = nullptr;
         HG_TRY(scratch_t<double>(S_OUT, size_t(nchunks) * size_t(npoints), &out));
         heget::Me2Args a{d_mom, npoints, nullptr, nullptr, npoints, nchunks,
-                         me2_coef(n, g_alpha, g_charge), out, npoints, d_flags};
+                         me2_coef(n, g_alpha, g_charge), out, npoints, nullptr, nullptr, d_flags};
         HG_HIP(heget::launch_me2(v, a, s));  // warm-up
         HG_HIP(hipEventRecord(e0, s));
         const int reps = 3;
@@ -1163,14 +1177,15 @@ heget_status heget_autotune(int n, heget_prec prec, int64_t npoints, heget_shape
         float t = 0.f;
         HG_HIP(hipEventElapsedTime(&t, e0, e1));
         const double per = double(t) / reps;
-        if (!best || per < best_ms) {
+        // a later shape must be 2% faster to win, so near-ties keep the
+        // earlier (default-first) table entry from run to run
+        if (!best || per < 0.98 * best_ms) {
             best = &v;
             best_ms = per;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    HG_TRY(scratch_release(s));
     if (!best) return fail(HEGET_ERR_ARG, "no compiled amplitude kernel for this n/precision");
     g_tuned[prec][n] = best;
     save_tuning_cache(*best, best_ms, npoints);
@@ -1273,10 +1288,14 @@ void heget_shutdown(void)
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g.ready) return;
     (void)hipDeviceSynchronize();
-    for (void *p : g.buf)
-        if (p) (void)hipFree(p);
-    g.buf.clear();
-    g.cap.clear();
+    for (Scratch &c : g.ctx) {
+        for (void *p : c.buf)
+            if (p) (void)hipFree(p);
+        c.buf.clear();
+        c.cap.clear();
+        c.bound = false;
+    }
+    g.cur = nullptr;
     for (hipEvent_t e : g.ev) (void)hipEventDestroy(e);
     g.ev.clear();
     g.ev_used = 0;
@@ -1291,8 +1310,6 @@ void heget_shutdown(void)
     g.fork = nullptr;
     if (g.pinned) (void)hipHostFree(g.pinned);
     g.pinned = nullptr;
-    if (g.ws_free) (void)hipEventDestroy(g.ws_free);
-    g.ws_free = nullptr;
     if (g.stream) (void)hipStreamDestroy(g.stream);
     g.stream = nullptr;
     g.ready = false;

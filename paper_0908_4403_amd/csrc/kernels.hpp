@@ -27,13 +27,15 @@ const Me2Variant *me2_default(int prec, int n);
 struct Me2Args {
     const double *mom;       // SoA [(n+2)*4][ld]
     int64_t ld;
-    const int32_t *index;    // survivor -> column of mom, or nullptr (identity)
+    const int32_t *index;    // survivor -> column of mom (and of wfac), or nullptr (identity)
     const int64_t *d_count;  // number of points on the device, or nullptr
     int64_t count;           // number of points when d_count is null; else an upper bound
     int nchunks;             // helicity chunks (each a separate work item)
     double coef;             // 2 (e Q)^(2n)
     double *out;             // [nchunks][ld_out]: |M|^2 of each chunk (summed over chunks)
     int64_t ld_out;
+    const double *wfac;      // per-point weight factor (with partials), else nullptr
+    double *partials;        // one chunk: per-tile weighted triples instead of out
     unsigned *flags;         // bit 0 set if a result is not finite
 };
 
@@ -41,7 +43,8 @@ hipError_t launch_me2(const Me2Variant &v, const Me2Args &a, hipStream_t stream)
 
 // Mixed-n batch: one persistent launch whose waves take (slice, tile, chunk)
 // work items from an atomic queue, slices in the given order (most expensive
-// per item first).  Each slice runs the default shape for its n.
+// per item first).  Each slice runs the batch shape for its n and writes
+// |M|^2 per chunk to `out` (its `wfac` and `partials` are not used).
 constexpr int kMaxSlices = 8;
 struct SliceDesc {
     const double *mom;
@@ -50,6 +53,8 @@ struct SliceDesc {
     const int64_t *d_count;
     double *out;
     int64_t ld_out;
+    const double *wfac;
+    double *partials;
     double coef;
     int n;
     int nchunks;
@@ -69,9 +74,10 @@ int me2_batch_blocks_per_cu(int prec);
 // (unrolled depth, helicities per walk, closing depth) of the mixed kernel for n
 void me2_batch_shape(int prec, int n, int *mb, int *h, int *cl);
 
-// Phase-space generation (FP64): momenta in SoA, weight (kind 0: Phi_n; kind
-// 1: full eq. (1)-(2) factor without |M|^2), accept flag, per-block accept
-// counts (blocks of 256 points).
+// Phase-space generation (FP64): momenta of every point in SoA and its
+// weight (kind 0: Phi_n or 0 if cut; kind 1: full eq. (1)-(2) factor without
+// |M|^2, or 0 if cut); optionally the accept flag per point and the accept
+// count per block of 256 points.
 hipError_t launch_gen(int n, const GenParams &g, double *mom, int64_t ld, double *w,
                       uint8_t *flag, int32_t *block_count, hipStream_t stream);
 // Exclusive scan of nb block counts -> offsets, total -> *d_count.
@@ -80,20 +86,18 @@ hipError_t launch_scan(const int32_t *counts, int nb, int32_t *offsets, int64_t 
 // Survivor list: index[offsets[b] + rank] = point, in point order.
 hipError_t launch_compact(const uint8_t *flag, int64_t np, const int32_t *offsets,
                           int32_t *index, hipStream_t stream);
-// Sum of helicity chunks, with optional indirection: out[k] = sum_c part[c*ld + k].
+
+// Sum of helicity chunks: out[k] = sum_c part[c*ld + k]; with `partials`, the
+// per-tile weighted triples of sum_c part * wfac[index[k]] instead (as the
+// amplitude kernel's one-chunk epilogue).
 hipError_t launch_sum_chunks(const double *part, int nchunks, int64_t ld, const int64_t *d_count,
-                             int64_t count, double *out, unsigned *flags, hipStream_t stream);
-// Weights w_k = me2[k] * wfac[index[k]] and per-block (sum, compensation, sum of squares).
-hipError_t launch_weights(const double *me2, const int32_t *index, const double *wfac,
-                          const int64_t *d_count, int64_t max_count, double *partials,
-                          unsigned *flags, hipStream_t stream);
-// Fixed-order compensated reduction of nb partial triples into res[0..2]
-// (sum, compensation, sum of squares) and res[3] = (double)*d_count.
-hipError_t launch_final(const double *partials, int nb, const int64_t *d_count, double *res,
-                        hipStream_t stream);
-// Result record {sigma, err, sum, comp, sum2 (double), n_gen, n_acc (int64)}
-// from res[0..3] = (sum, comp, sum2, n_acc) and n_gen, written to out.
-hipError_t launch_result(const double *res, int64_t n_gen, void *out, hipStream_t stream);
+                             int64_t count, double *out, const int32_t *index, const double *wfac,
+                             double *partials, unsigned *flags, hipStream_t stream);
+// Fixed-order compensated reduction of the ceil(*d_count / 64) tile triples
+// into res[0..3] = (sum + compensation, compensation, sum of squares, *d_count)
+// and, if `record` is set, the heget_result record for n_gen generated points.
+hipError_t launch_final(const double *partials, const int64_t *d_count, int64_t n_gen, double *res,
+                        void *record, hipStream_t stream);
 // Zero a small device buffer with a kernel (usable under stream capture).
 hipError_t launch_zero_u32(unsigned *p, int count, hipStream_t stream);
 

@@ -33,7 +33,7 @@ __device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t poi
         const double c = 2.0 * ucos - 1.0;
         const double s = sqrt(1.0 - c * c);
         double sf, cf;
-        sincos(2.0 * M_PI * uphi, &sf, &cf);
+        sincospi(2.0 * uphi, &sf, &cf);  // azimuth 2 pi uphi, reduced exactly
         const double e = -log(ue1 * ue2);
         k[i] = {e, e * s * cf, e * s * sf, e * c};
         Qe += k[i].e;
@@ -58,7 +58,8 @@ __device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t poi
 }
 
 // 1 if every photon has pT > pt_min and |eta + y| < eta_max and every pair
-// Delta R > dr_min (bounds <= 0 are off).  eta = atanh(pz/|p|).
+// Delta R > dr_min (bounds <= 0 are off).  eta = atanh(pz/|p|), evaluated as
+// sign(pz) log((|p| + |pz|) / pT), which has no cancellation near the beam.
 template <int N>
 __device__ __forceinline__ bool pass_cuts(const Vec4 (&k)[N], double y, double pt_min,
                                           double eta_max, double dr_min)
@@ -70,7 +71,7 @@ __device__ __forceinline__ bool pass_cuts(const Vec4 (&k)[N], double y, double p
         const double pt2 = k[i].x * k[i].x + k[i].y * k[i].y;
         const double pt = sqrt(pt2);
         const double pabs = sqrt(pt2 + k[i].z * k[i].z);
-        eta[i] = atanh(k[i].z / pabs) + y;
+        eta[i] = copysign(log((pabs + fabs(k[i].z)) / pt), k[i].z) + y;
         phi[i] = atan2(k[i].y, k[i].x);
         if (pt_min > 0.0) ok = ok && (pt > pt_min);
         if (eta_max > 0.0) ok = ok && (fabs(eta[i]) < eta_max);
@@ -103,6 +104,7 @@ struct GenParams {
     double partonic_coef;
     double phase_volume_coef;
     int weight_kind;     // 0: write Phi_n (or 0 if cut); 1: write the full non-|M|^2 weight
+    unsigned *clear_word;  // if set, zeroed by the generation launch (the call's status flags)
 };
 
 struct PointKin {

@@ -1,53 +1,73 @@
 // Monte-Carlo side of the path: phase-space generation with cuts, stream
-// compaction of the surviving points, per-point weights of eq. (1)-(2) and a
-// deterministic compensated reduction.  All FP64.
+// compaction of the surviving points into an index list; per-point weights of
+// eq. (1)-(2) are applied in the amplitude pass; a deterministic compensated
+// reduction gives sigma and its error.  All FP64.
 //
 // Determinism: compaction keeps point order (block counts -> exclusive scan
-// -> in-block ballot ranks), and every sum is a fixed tree (lanes by xor
-// shuffles, waves through LDS, blocks in index order), so a configuration
-// gives bitwise the same sigma on every run.
+// -> in-block ballot ranks), and every sum is a fixed tree (64-point tiles by
+// xor shuffles, tiles in index order), so a configuration gives bitwise the
+// same sigma on every run.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 #include "kernels.hpp"
+#include "reduce.hpp"
 
 namespace heget {
 
+// Kinematics, cut decision and weight of one point.
+template <int N>
+__device__ __forceinline__ void point_setup(const GenParams &g, uint64_t point, Vec4 (&k)[N],
+                                            double &e_beam, double &w, bool &acc)
+{
+    const PointKin pk = point_kinematics(g, point);
+    rambo<N>(pk.sqrt_shat, g.seed, point, k);
+    acc = pk.above && pass_cuts<N>(k, pk.y, g.pt_min, g.eta_max, g.dr_min);
+    e_beam = 0.5 * pk.sqrt_shat;
+    const double shat = pk.sqrt_shat * pk.sqrt_shat;
+    if (g.weight_kind == 0)
+        w = g.phase_volume_coef * ipow(shat, N - 2);
+    else
+        w = g.partonic_coef * ipow(shat, N - 3) * pk.fpdf;
+}
+
+// SoA rows of one point: quark momenta (E, 0, 0, +-E), then the photons.
+template <int N>
+__device__ __forceinline__ void store_point(double *__restrict__ mom, int64_t ld, int64_t col,
+                                            double e, const Vec4 (&k)[N])
+{
+    mom[0 * ld + col] = e;
+    mom[1 * ld + col] = 0.0;
+    mom[2 * ld + col] = 0.0;
+    mom[3 * ld + col] = e;
+    mom[4 * ld + col] = e;
+    mom[5 * ld + col] = 0.0;
+    mom[6 * ld + col] = 0.0;
+    mom[7 * ld + col] = -e;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        mom[(8 + 4 * j) * ld + col] = k[j].e;
+        mom[(9 + 4 * j) * ld + col] = k[j].x;
+        mom[(10 + 4 * j) * ld + col] = k[j].y;
+        mom[(11 + 4 * j) * ld + col] = k[j].z;
+    }
+}
+
+// Every point, in point order; rejected points keep their momenta, weight 0.
+// Optionally the accept flag per point and the accept count per block of 256.
 template <int N>
 __global__ void __launch_bounds__(256)
 gen_kernel(GenParams g, double *__restrict__ mom, int64_t ld, double *__restrict__ wout,
            uint8_t *__restrict__ flag, int32_t *__restrict__ block_count)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (g.clear_word && i == 0) *g.clear_word = 0u;
     bool acc = false;
     if (i < g.npoints) {
-        const uint64_t point = static_cast<uint64_t>(g.first + i);
-        const PointKin pk = point_kinematics(g, point);
         Vec4 k[N];
-        rambo<N>(pk.sqrt_shat, g.seed, point, k);
-        acc = pk.above && pass_cuts<N>(k, pk.y, g.pt_min, g.eta_max, g.dr_min);
-        const double e = 0.5 * pk.sqrt_shat;
-        mom[0 * ld + i] = e;
-        mom[1 * ld + i] = 0.0;
-        mom[2 * ld + i] = 0.0;
-        mom[3 * ld + i] = e;
-        mom[4 * ld + i] = e;
-        mom[5 * ld + i] = 0.0;
-        mom[6 * ld + i] = 0.0;
-        mom[7 * ld + i] = -e;
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            mom[(8 + 4 * j) * ld + i] = k[j].e;
-            mom[(9 + 4 * j) * ld + i] = k[j].x;
-            mom[(10 + 4 * j) * ld + i] = k[j].y;
-            mom[(11 + 4 * j) * ld + i] = k[j].z;
-        }
-        const double shat = pk.sqrt_shat * pk.sqrt_shat;
-        double w;
-        if (g.weight_kind == 0)
-            w = g.phase_volume_coef * ipow(shat, N - 2);
-        else
-            w = g.partonic_coef * ipow(shat, N - 3) * pk.fpdf;
+        double e, w;
+        point_setup<N>(g, static_cast<uint64_t>(g.first + i), k, e, w, acc);
+        store_point<N>(mom, ld, i, e, k);
         wout[i] = acc ? w : 0.0;
         if (flag) flag[i] = acc ? 1 : 0;
     }
@@ -85,6 +105,7 @@ scan_kernel(const int32_t *__restrict__ counts, int nb, int32_t *__restrict__ of
     if (t == 1023) *total = part[1023];
 }
 
+// Survivor list: index[offsets[b] + rank] = point, in point order.
 __global__ void __launch_bounds__(256)
 compact_kernel(const uint8_t *__restrict__ flag, int64_t np, const int32_t *__restrict__ offsets,
                int32_t *__restrict__ index)
@@ -102,13 +123,29 @@ compact_kernel(const uint8_t *__restrict__ flag, int64_t np, const int32_t *__re
     if (f) index[base + rank] = static_cast<int32_t>(i);
 }
 
+// ---------------------------------------------------------------- sums
+
 __global__ void __launch_bounds__(256)
 sum_chunks_kernel(const double *__restrict__ part, int nchunks, int64_t ld,
                   const int64_t *__restrict__ d_count, int64_t count, double *__restrict__ out,
-                  unsigned *__restrict__ flags)
+                  const int32_t *__restrict__ index, const double *__restrict__ wfac,
+                  double *__restrict__ partials, unsigned *__restrict__ flags)
 {
     const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     const int64_t n = d_count ? *d_count : count;
+    if (partials) {
+        // whole waves stay for the tile reduction
+        if ((k & ~int64_t(63)) >= n) return;
+        double w = 0.0;
+        if (k < n) {
+            double s = 0.0;
+            for (int c = 0; c < nchunks; ++c) s += part[c * ld + k];
+            w = s * wfac[index ? static_cast<int64_t>(index[k]) : k];
+            if (!isfinite(w)) atomicOr(flags, 1u);
+        }
+        tile_partial(w, threadIdx.x & 63, partials, k >> 6);
+        return;
+    }
     if (k >= n) return;
     double s = 0.0;
     for (int c = 0; c < nchunks; ++c) s += part[c * ld + k];
@@ -116,35 +153,15 @@ sum_chunks_kernel(const double *__restrict__ part, int nchunks, int64_t ld,
     out[k] = s;
 }
 
-// (sum, compensation) pairs combined with an error-free two-sum.
-struct CSum {
-    double s, c;
-};
+constexpr int kFinalThreads = 1024;
+constexpr int kFinalBatch = 8;
 
-__device__ __forceinline__ CSum csum_add(CSum a, CSum b)
-{
-    const double t = a.s + b.s;
-    const double bb = t - a.s;
-    const double err = (a.s - (t - bb)) + (b.s - bb);
-    return {t, a.c + b.c + err};
-}
-
-__device__ __forceinline__ double shfl_xor_d(double v, int m)
-{
-    return __shfl_xor(v, m, 64);
-}
-
-// Block (256 threads) reduction of (sum, compensation, sum of squares) into thread 0.
+// Block reduction of (sum, compensation, sum of squares) into thread 0.
 __device__ __forceinline__ void block_reduce(CSum &cs, double &sq)
 {
-    __shared__ double sh[3][4];
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const CSum o{shfl_xor_d(cs.s, m), shfl_xor_d(cs.c, m)};
-        const double osq = shfl_xor_d(sq, m);
-        cs = csum_add(cs, o);
-        sq += osq;
-    }
+    constexpr int kWaves = kFinalThreads / 64;
+    __shared__ double sh[3][kWaves];
+    wave_reduce(cs, sq);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) {
         sh[0][w] = cs.s;
@@ -155,75 +172,63 @@ __device__ __forceinline__ void block_reduce(CSum &cs, double &sq)
     if (threadIdx.x == 0) {
         cs = {sh[0][0], sh[1][0]};
         sq = sh[2][0];
-        for (int k = 1; k < 4; ++k) {
-            cs = csum_add(cs, CSum{sh[0][k], sh[1][k]});
-            sq += sh[2][k];
+        for (int q = 1; q < kWaves; ++q) {
+            cs = csum_add(cs, CSum{sh[0][q], sh[1][q]});
+            sq += sh[2][q];
         }
     }
 }
 
-__global__ void __launch_bounds__(256)
-weights_kernel(const double *__restrict__ me2, const int32_t *__restrict__ index,
-               const double *__restrict__ wfac, const int64_t *__restrict__ d_count,
-               double *__restrict__ partials, unsigned *__restrict__ flags)
+// One block: thread t folds tiles t, t + T, t + 2T, ... in that order (loads
+// issued kFinalBatch at a time), then a fixed tree.  The record is {sigma,
+// err, sum, comp, sum2 (double), n_gen, n_acc (int64)}, sigma = sum / n_gen
+// and err^2 = (sum2/N - sigma^2)/(N - 1).
+__global__ void __launch_bounds__(kFinalThreads)
+final_kernel(const double *__restrict__ partials, const int64_t *__restrict__ d_count,
+             int64_t n_gen, double *__restrict__ res, void *record)
 {
-    const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    const int64_t n = *d_count;
-    double w = 0.0;
-    if (k < n) {
-        w = me2[k] * wfac[index[k]];
-        if (!isfinite(w)) atomicOr(flags, 1u);
-    }
-    CSum cs{w, 0.0};
-    double sq = w * w;
-    block_reduce(cs, sq);
-    if (threadIdx.x == 0) {
-        partials[3 * blockIdx.x + 0] = cs.s;
-        partials[3 * blockIdx.x + 1] = cs.c;
-        partials[3 * blockIdx.x + 2] = sq;
-    }
-}
-
-__global__ void __launch_bounds__(256)
-final_kernel(const double *__restrict__ partials, int nb, const int64_t *__restrict__ d_count,
-             double *__restrict__ res)
-{
-    // each thread folds a contiguous range in order, then a fixed tree
+    const int64_t nacc = *d_count;
+    const int64_t nt = (nacc + 63) / 64;
     const int t = threadIdx.x;
-    const int per = (nb + 255) / 256;
-    const int beg = min(t * per, nb), end = min(beg + per, nb);
     CSum cs{0.0, 0.0};
     double sq = 0.0;
-    for (int j = beg; j < end; ++j) {
-        cs = csum_add(cs, CSum{partials[3 * j], partials[3 * j + 1]});
-        sq += partials[3 * j + 2];
+    for (int64_t j0 = t; j0 < nt; j0 += int64_t(kFinalThreads) * kFinalBatch) {
+        double v[kFinalBatch][3];
+#pragma unroll
+        for (int u = 0; u < kFinalBatch; ++u) {
+            const int64_t j = j0 + int64_t(u) * kFinalThreads;
+            const bool in = j < nt;
+            v[u][0] = in ? partials[3 * j + 0] : 0.0;
+            v[u][1] = in ? partials[3 * j + 1] : 0.0;
+            v[u][2] = in ? partials[3 * j + 2] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kFinalBatch; ++u) {
+            cs = csum_add(cs, CSum{v[u][0], v[u][1]});
+            sq += v[u][2];
+        }
     }
     block_reduce(cs, sq);
-    if (t == 0) {
-        res[0] = cs.s + cs.c;
-        res[1] = cs.c;
-        res[2] = sq;
-        res[3] = static_cast<double>(*d_count);
+    if (t != 0) return;
+    const double sum = cs.s + cs.c;
+    res[0] = sum;
+    res[1] = cs.c;
+    res[2] = sq;
+    res[3] = static_cast<double>(nacc);
+    if (record) {
+        double *d = static_cast<double *>(record);
+        int64_t *q = static_cast<int64_t *>(record);
+        const double N = static_cast<double>(n_gen);
+        const double sigma = n_gen > 0 ? sum / N : 0.0;
+        const double var = n_gen > 1 ? (sq / N - sigma * sigma) / (N - 1.0) : 0.0;
+        d[0] = sigma;
+        d[1] = sqrt(var > 0.0 ? var : 0.0);
+        d[2] = sum;
+        d[3] = cs.c;
+        d[4] = sq;
+        q[5] = n_gen;
+        q[6] = nacc;
     }
-}
-
-// sigma = sum/N and its MC error written as the heget_result layout
-// {sigma, err, sum, comp, sum2, n_gen, n_acc} (five doubles, two int64).
-__global__ void result_kernel(const double *__restrict__ res, int64_t n_gen, void *out)
-{
-    double *d = static_cast<double *>(out);
-    int64_t *q = static_cast<int64_t *>(out);
-    const double sum = res[0], sum2 = res[2];
-    const double N = static_cast<double>(n_gen);
-    const double sigma = n_gen > 0 ? sum / N : 0.0;
-    const double var = n_gen > 1 ? (sum2 / N - sigma * sigma) / (N - 1.0) : 0.0;
-    d[0] = sigma;
-    d[1] = sqrt(var > 0.0 ? var : 0.0);
-    d[2] = sum;
-    d[3] = res[1];
-    d[4] = sum2;
-    q[5] = n_gen;
-    q[6] = static_cast<int64_t>(res[3]);
 }
 
 __global__ void zero_u32_kernel(unsigned *p, int count)
@@ -278,41 +283,27 @@ hipError_t launch_compact(const uint8_t *flag, int64_t np, const int32_t *offset
 }
 
 hipError_t launch_sum_chunks(const double *part, int nchunks, int64_t ld, const int64_t *d_count,
-                             int64_t count, double *out, unsigned *flags, hipStream_t stream)
+                             int64_t count, double *out, const int32_t *index, const double *wfac,
+                             double *partials, unsigned *flags, hipStream_t stream)
 {
     const int64_t blocks = (count + 255) / 256;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(sum_chunks_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
-                       part, nchunks, ld, d_count, count, out, flags);
+                       part, nchunks, ld, d_count, count, out, index, wfac, partials, flags);
     return hipGetLastError();
 }
 
-hipError_t launch_weights(const double *me2, const int32_t *index, const double *wfac,
-                          const int64_t *d_count, int64_t max_count, double *partials,
-                          unsigned *flags, hipStream_t stream)
+hipError_t launch_final(const double *partials, const int64_t *d_count, int64_t n_gen, double *res,
+                        void *record, hipStream_t stream)
 {
-    const int64_t blocks = (max_count + 255) / 256;
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(weights_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
-                       me2, index, wfac, d_count, partials, flags);
-    return hipGetLastError();
-}
-
-hipError_t launch_final(const double *partials, int nb, const int64_t *d_count, double *res,
-                        hipStream_t stream)
-{
-    hipLaunchKernelGGL(final_kernel, dim3(1), dim3(256), 0, stream, partials, nb, d_count, res);
-    return hipGetLastError();
-}
-
-hipError_t launch_result(const double *res, int64_t n_gen, void *out, hipStream_t stream)
-{
-    hipLaunchKernelGGL(result_kernel, dim3(1), dim3(1), 0, stream, res, n_gen, out);
+    hipLaunchKernelGGL(final_kernel, dim3(1), dim3(kFinalThreads), 0, stream, partials, d_count,
+                       n_gen, res, record);
     return hipGetLastError();
 }
 
 hipError_t launch_zero_u32(unsigned *p, int count, hipStream_t stream)
 {
+    if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(zero_u32_kernel, dim3((count + 255) / 256), dim3(256), 0, stream, p, count);
     return hipGetLastError();
 }

@@ -40,8 +40,10 @@ template <typename R, int N>
 __device__ __forceinline__ void batch_item(const SliceDesc &d, int64_t npts, int64_t tile, int chunk,
                                            unsigned *flags, R *tab, int lane)
 {
-    me2_item<R, N, BatchShape<R>::mb(N), BatchShape<R>::h, BatchShape<R>::cl>(
-        d.mom, d.ld, d.index, npts, tile, chunk, d.nchunks, d.coef, d.out, d.ld_out, flags, tab, lane);
+    // |M|^2 only: the weighted sums follow in a separate pass
+    me2_item<R, N, BatchShape<R>::mb(N), BatchShape<R>::h, BatchShape<R>::cl, false>(
+        d.mom, d.ld, d.index, npts, tile, chunk, d.nchunks, d.coef, d.out, d.ld_out, d.wfac,
+        d.partials, flags, tab, lane);
 }
 
 template <typename R>
@@ -53,8 +55,11 @@ __global__ void __launch_bounds__(256) me2_batch_kernel(BatchDesc b)
     R *tab = tab_all + wave * kPhotonFields * 8 * 64;
     const int64_t total = b.item_start[b.nslices];
     for (;;) {
+        // the first active lane takes the next item, so the queue advances on
+        // every pass whichever lanes the compiled loop keeps active
         int64_t item = 0;
-        if (lane == 0) item = static_cast<int64_t>(atomicAdd(b.queue, 1ull));
+        if (lane == __builtin_amdgcn_readfirstlane(lane))
+            item = static_cast<int64_t>(atomicAdd(b.queue, 1ull));
         item = wave_broadcast(item);
         if (item >= total) break;
         int s = 0;

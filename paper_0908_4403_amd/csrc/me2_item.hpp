@@ -9,16 +9,24 @@
 
 #include "kernels.hpp"
 #include "me2_tree.hpp"
+#include "reduce.hpp"
 
 namespace heget {
 
 // One work item: 64 points (one per lane) x one chunk of helicity walks.
 // `tab` is this wave's LDS photon table (kPhotonFields * N * 64 values of R).
-template <typename R, int N, int MB, int H, int CL>
+// Point i of the item is column index[i] of mom (column i without an index).
+// Output: with kWeighted, `partials` set and one chunk, the tile's (sum,
+// compensation, sum of squares) of |M|^2 * wfac[column] (the Monte-Carlo
+// weights of eq. (1)-(2)); otherwise |M|^2 of the chunk at
+// out[chunk * ld_out + i].
+template <typename R, int N, int MB, int H, int CL, bool kWeighted = true>
 __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t ld,
                                          const int32_t *__restrict__ index, int64_t npts,
                                          int64_t tile, int chunk, int nchunks, double coef,
                                          double *__restrict__ out, int64_t ld_out,
+                                         const double *__restrict__ wfac,
+                                         double *__restrict__ partials,
                                          unsigned *__restrict__ flags, R *tab, int lane)
 {
     constexpr bool kTopInLds = N > MB;
@@ -72,7 +80,11 @@ __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t
     const double s = tree_sum<R, N, MB, H, CL>(in, tab, lane, chunk * ppc, (chunk + 1) * ppc);
     double me2 = ldexp(coef * norm * s, 2 * m * (2 - N));
     if (!ok) me2 = __builtin_nan("");
-    if (valid) {
+    if (kWeighted && partials && nchunks == 1) {
+        const double w = valid ? me2 * wfac[src] : 0.0;
+        if (!isfinite(w)) atomicOr(flags, 1u);
+        tile_partial(w, lane, partials, tile);
+    } else if (valid) {
         if (!isfinite(me2)) atomicOr(flags, 1u);
         out[static_cast<int64_t>(chunk) * ld_out + i] = me2;
     }
@@ -81,8 +93,9 @@ __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t
 template <typename R, int N, int MB, int H, int CL, int WPB>
 __global__ void __launch_bounds__(WPB * 64)
 me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict__ index,
-           const int64_t *__restrict__ d_count, int64_t count, int nchunks, double coef,
-           double *__restrict__ out, int64_t ld_out, unsigned *__restrict__ flags)
+           const int64_t *__restrict__ d_count, int64_t count, int nchunks, double coef, double *__restrict__ out, int64_t ld_out,
+           const double *__restrict__ wfac, double *__restrict__ partials,
+           unsigned *__restrict__ flags)
 {
     __shared__ R tab_all[N > MB ? WPB * kPhotonFields * N * 64 : 1];
     const int lane = threadIdx.x & 63;
@@ -94,8 +107,8 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
     const int64_t tile = item / nchunks;
     const int chunk = static_cast<int>(item - tile * nchunks);
     R *tab = tab_all + (N > MB ? wave * kPhotonFields * N * 64 : 0);
-    me2_item<R, N, MB, H, CL>(mom, ld, index, npts, tile, chunk, nchunks, coef, out, ld_out, flags,
-                              tab, lane);
+    me2_item<R, N, MB, H, CL>(mom, ld, index, npts, tile, chunk, nchunks, coef, out, ld_out, wfac,
+                              partials, flags, tab, lane);
 }
 
 template <typename R, int N, int MB, int H, int CL, int WPB>

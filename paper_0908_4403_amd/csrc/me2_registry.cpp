@@ -48,10 +48,11 @@ hipError_t launch_me2(const Me2Variant &v, const Me2Args &a, hipStream_t stream)
     if (items == 0) return hipSuccess;
     const int64_t blocks = (items + v.wpb - 1) / v.wpb;
     void *args[] = {const_cast<double **>(&a.mom), const_cast<int64_t *>(&a.ld),
-                    const_cast<int32_t **>(&a.index), const_cast<int64_t **>(&a.d_count),
-                    const_cast<int64_t *>(&a.count), const_cast<int *>(&a.nchunks),
-                    const_cast<double *>(&a.coef), const_cast<double **>(&a.out),
-                    const_cast<int64_t *>(&a.ld_out), const_cast<unsigned **>(&a.flags)};
+                    const_cast<int32_t **>(&a.index), const_cast<int64_t **>(&a.d_count), const_cast<int64_t *>(&a.count),
+                    const_cast<int *>(&a.nchunks), const_cast<double *>(&a.coef),
+                    const_cast<double **>(&a.out), const_cast<int64_t *>(&a.ld_out),
+                    const_cast<double **>(&a.wfac), const_cast<double **>(&a.partials),
+                    const_cast<unsigned **>(&a.flags)};
     return hipLaunchKernel(v.func, dim3(static_cast<unsigned>(blocks)), dim3(v.wpb * 64), args, 0,
                            stream);
 }

@@ -20,14 +20,15 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hiA = __umulhi(kMulA, c0), loA = kMulA * c0;
-        const uint32_t hiB = __umulhi(kMulB, c2), loB = kMulB * c2;
-        const uint32_t t0 = hiB ^ c1 ^ k0;
-        const uint32_t t2 = hiA ^ c3 ^ k1;
+        // one 32x32->64 multiply gives both halves of each product
+        const uint64_t pA = static_cast<uint64_t>(kMulA) * c0;
+        const uint64_t pB = static_cast<uint64_t>(kMulB) * c2;
+        const uint32_t t0 = static_cast<uint32_t>(pB >> 32) ^ c1 ^ k0;
+        const uint32_t t2 = static_cast<uint32_t>(pA >> 32) ^ c3 ^ k1;
         c0 = t0;
-        c1 = loB;
+        c1 = static_cast<uint32_t>(pB);
         c2 = t2;
-        c3 = loA;
+        c3 = static_cast<uint32_t>(pA);
         k0 += kWeylA;
         k1 += kWeylB;
     }
