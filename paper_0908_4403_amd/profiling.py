@@ -11,7 +11,7 @@ HBM bytes per launch of the kernel.
         --fetch run_fetch/counter_collection.csv --write run_write/counter_collection.csv \\
         --kernel "me2_kernel<float,4,4,16,2,1>" --out profiles/NAME.md --command "..."
 
-    python -m paper_0908_4403_amd.profiling trace --stats kernel_stats.csv \\
+    python -m paper_0908_4403_amd.profiling trace --trace kernel_trace.csv \\
         --out profiles/NAME.md --command "..." [--title "..."]
 
 The traffic summary records a digest of the device sources (csrc/); a
@@ -142,28 +142,25 @@ def read_traffic(md_path: str, kernel: str):
     return float(b.group(1))
 
 
-def trace_markdown(stats_csv: str, command: str, title: str, top: int = 12) -> str:
-    """Kernel-trace statistics (rocprofv3 --stats kernel_stats.csv) as a table."""
-    rows = []
-    with open(_find_csv(stats_csv, "kernel_stats.csv"), newline="") as f:
+def trace_markdown(trace_csv: str, command: str, title: str, top: int = 14) -> str:
+    """Per-(kernel, grid) statistics of a rocprofv3 --kernel-trace run
+    (kernel_trace.csv), so launches of one kernel at different sizes (the
+    autotuner's, the timed steps') are not averaged together."""
+    groups = {}
+    with open(_find_csv(trace_csv, "kernel_trace.csv"), newline="") as f:
         for r in csv.DictReader(f):
-            rows.append(r)
-
-    def num(r, *keys):
-        for k in keys:
-            if k in r and r[k] not in ("", None):
-                return float(r[k])
-        return 0.0
-
-    rows.sort(key=lambda r: -num(r, "TotalDurationNs", "TotalDuration"))
+            grid = int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0)
+            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            groups.setdefault((short_name(r["Kernel_Name"]), grid), []).append(dur)
+    total = sum(sum(v) for v in groups.values()) or 1.0
+    rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))
     lines = [f"# {title}", "", "Command (GPU box, from the repository root):", "", "    " + command, "",
-             "Durations in microseconds.", "",
-             "| kernel | calls | total us | average us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
-    for r in rows[:top]:
-        lines.append("| `{}` | {:.0f} | {:.1f} | {:.1f} | {:.1f} | {:.1f} | {:.1f} |".format(
-            short_name(r.get("Name", r.get("KernelName", ""))), num(r, "Calls"),
-            num(r, "TotalDurationNs") / 1e3, num(r, "AverageNs") / 1e3, num(r, "MinNs") / 1e3,
-            num(r, "MaxNs") / 1e3, num(r, "Percentage")))
+             "Durations in microseconds, per kernel and launch size (grid = threads).", "",
+             "| kernel | grid | calls | total us | average us | min us | max us | % |",
+             "|---|---|---|---|---|---|---|---|"]
+    for (name, grid), d in rows[:top]:
+        lines.append(f"| `{name}` | {grid} | {len(d)} | {sum(d):.1f} | {sum(d) / len(d):.1f} | "
+                     f"{min(d):.1f} | {max(d):.1f} | {100 * sum(d) / total:.1f} |")
     return "\n".join(lines) + "\n"
 
 
@@ -178,7 +175,7 @@ def main(argv=None):
     t.add_argument("--command", required=True)
     t.add_argument("--title", default="HBM traffic of the amplitude kernel")
     s = sub.add_parser("trace")
-    s.add_argument("--stats", required=True)
+    s.add_argument("--trace", required=True, help="kernel_trace.csv or the folder holding it")
     s.add_argument("--out", required=True)
     s.add_argument("--command", required=True)
     s.add_argument("--title", default="rocprofv3 kernel trace")
@@ -187,7 +184,7 @@ def main(argv=None):
         tr = traffic(a.fetch, a.write, a.kernel)
         text = traffic_markdown(a.kernel.replace(" ", ""), tr, a.command, a.title)
     else:
-        text = trace_markdown(a.stats, a.command, a.title)
+        text = trace_markdown(a.trace, a.command, a.title)
     with open(a.out, "w") as f:
         f.write(text)
     print(text)

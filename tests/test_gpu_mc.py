@@ -129,3 +129,20 @@ def test_xsec_device_and_async_match_sync(H):
     torch.cuda.synchronize()
     assert H.result_from_bytes(buf.cpu().numpy()) == ref
     assert h.result() == ref
+
+
+def test_back_to_back_calls_match_one_by_one(H):
+    """Five calls enqueued back to back on one stream (different seeds and
+    sizes, sharing the stream's scratch) equal the same five made one at a
+    time."""
+    import torch
+    cfgs = [H.Config(prec=H.FP32, seed=20 + k, npoints=30000 + 7919 * k, sqrt_s=1000.0)
+            for k in range(5)]
+    ref = [H.xsec(4, c) for c in cfgs]
+    buf = torch.zeros((len(cfgs), 64), dtype=torch.uint8, device="cuda")
+    for k, c in enumerate(cfgs):
+        H.xsec_device(4, c, buf[k])
+    torch.cuda.synchronize()
+    host = buf.cpu().numpy()
+    for k in range(len(cfgs)):
+        assert H.result_from_bytes(host[k]) == ref[k], k
