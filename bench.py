@@ -105,6 +105,44 @@ def mixed_batch(H, torch, prec, steps):
             "sigma_fb": {str(n): r["sigma_fb"] for n, r in zip(ns, res)}}
 
 
+def per_n(H, torch, tune):
+    """Amplitude kernel alone (heget_me2_device) for n = 2..8 on device-generated
+    points (sqrt(shat) = 1 TeV, seed 11, no cuts so every point is a valid input),
+    FP32 and FP64, with HIP-event timing of the kernel on its launch stream."""
+    out = []
+    for n in range(2, 9):
+        npts = 1 << {2: 22, 3: 21, 4: 20, 5: 18, 6: 16, 7: 15, 8: 14}[n]
+        mom = torch.empty(((n + 2) * 4, npts), dtype=torch.float64, device="cuda")
+        w = torch.empty(npts, dtype=torch.float64, device="cuda")
+        H.gen_points_device(n, 1000.0, mom, w, None, 11)
+        me2 = torch.empty(npts, dtype=torch.float64, device="cuda")
+        row = {"n": n, "points": npts}
+        for prec, name in ((H.FP32, "fp32"), (H.FP64, "fp64")):
+            if tune:
+                H.autotune(n, prec, min(npts, 1 << 18))
+            H.me2_device(n, mom, me2, prec)  # warm-up
+            torch.cuda.synchronize()
+            H.timing_enable(True)
+            H.timing_read(reset=True)
+            reps = 3
+            for _ in range(reps):
+                H.me2_device(n, mom, me2, prec)
+            torch.cuda.synchronize()
+            ms, launches = H.timing_read(reset=True)
+            H.timing_enable(False)
+            ms /= max(launches, 1)
+            f, shape = H.me2_flops(n, prec)
+            tf = f * npts / (ms * 1e-3) / 1e12
+            row[name] = {"points_per_s": npts / (ms * 1e-3), "kernel_ms": ms, "tflops": tf,
+                         "frac": tf / PEAK_VALU_TFLOPS, "shape": shape, "flops_per_point": f}
+        print(f"bench: per-n n={n} FP32 {row['fp32']['points_per_s']:.3e} pts/s "
+              f"({row['fp32']['frac']:.2f}), FP64 {row['fp64']['points_per_s']:.3e} "
+              f"({row['fp64']['frac']:.2f})", file=sys.stderr, flush=True)
+        out.append(row)
+        del mom, w, me2
+    return out
+
+
 def cpu_baseline(n, wl, budget_s):
     """FP64 oracle |M|^2 on the first survivors of the same stream (~budget_s of CPU)."""
     import numpy as np
@@ -142,6 +180,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed n=2..7 batch")
     ap.add_argument("--no-tune", action="store_true", help="use the untuned kernel shapes")
+    ap.add_argument("--per-n", action="store_true",
+                    help="also time the amplitude kernel alone for n = 2..8 (FP32 and FP64)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for rocprofv3 FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -194,11 +234,16 @@ def main():
         print(f"bench: mixed batch {mixed['batch_ms']:.2f} ms vs per-n {mixed['one_launch_per_n_ms']:.2f} ms",
               file=sys.stderr, flush=True)
 
+    pern = per_n(H, torch, not args.no_tune) if args.per_n else None
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(n, wl, args.cpu_seconds)
 
+    peak = H.valu_peak()
+    print(f"bench: measured FMA ceiling FP32 {peak['fp32_tflops']:.1f}, FP64 {peak['fp64_tflops']:.1f} TFLOP/s",
+          file=sys.stderr, flush=True)
     kname = f"me2_kernel<float,{n},{shape32[0]},{shape32[1]},{shape32[2]},{shape32[3]}>"
     from paper_0908_4403_amd.profiling import read_traffic
     traffic_md = os.path.join(ROOT, "profiles", f"me2_kernel_{args.workload}_hbm_traffic.md")
@@ -227,14 +272,18 @@ def main():
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": kname,
                      "kernel_ms": k32,
-                     "flops_per_point": f32, "frac_of_published_fp32_vector": ach32 / PUBLISHED_FP32_VECTOR_TFLOPS},
+                     "flops_per_point": f32, "frac_of_published_fp32_vector": ach32 / PUBLISHED_FP32_VECTOR_TFLOPS,
+                     "measured_fma_ceiling": peak["fp32_tflops"],
+                     "frac_of_measured_ceiling": ach32 / peak["fp32_tflops"]},
         "fp64_plain": {"value": r64["n_acc"] / (ms64 * 1e-3), "ms_per_step": ms64, "kernel_ms": k64,
                        "achieved_tflops": ach64, "frac": ach64 / PEAK_VALU_TFLOPS,
+                       "frac_of_measured_ceiling": ach64 / peak["fp64_tflops"],
                        "sigma_fb": r64["sigma_fb"], "flops_per_point": f64},
         "fp32_over_fp64": (n_acc / ms32) / (r64["n_acc"] / ms64),
         "generated_points_per_s": wl["npoints"] / (ms32 * 1e-3),
         "tuned_shapes": tuned,
         "mixed_batch": mixed,
+        "per_n": pern,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

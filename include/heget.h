@@ -226,6 +226,12 @@ heget_status heget_kernel_shapes(int n, heget_prec prec, int max, heget_shape *s
  * restores the default.  HEGET_ERR_ARG if no such shape was compiled. */
 heget_status heget_set_kernel_shape(int n, heget_prec prec, const heget_shape *shape);
 
+/* Vector-ALU ceiling of the current device: the FP32 and FP64 FMA rates (in
+ * TFLOP/s, FMA = 2 flops) of a kernel of independent FMA chains with no
+ * memory traffic, built like the amplitude kernels (no packed FP32).  Either
+ * pointer may be NULL.  Takes a few tens of milliseconds. */
+heget_status heget_valu_peak(double *fp32_tflops, double *fp64_tflops);
+
 /* Message of the last failure on this thread ("" if none). */
 const char *heget_last_error(void);
 

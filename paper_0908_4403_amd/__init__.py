@@ -41,7 +41,7 @@ EXPORTS = ["heget_gen_points", "heget_gen_points_device", "heget_me2", "heget_me
            "heget_set_couplings",
            "heget_timing_enable",
            "heget_timing_read", "heget_me2_flops", "heget_autotune", "heget_kernel_shapes",
-           "heget_set_kernel_shape",
+           "heget_set_kernel_shape", "heget_valu_peak",
            "heget_last_error", "heget_shutdown"]
 
 
@@ -110,6 +110,7 @@ def _load():
     lib.heget_kernel_shapes.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(Shape),
                                         C.POINTER(C.c_int)]
     lib.heget_set_kernel_shape.argtypes = [C.c_int, C.c_int, C.POINTER(Shape)]
+    lib.heget_valu_peak.argtypes = [_dp, _dp]
     lib.heget_last_error.restype = C.c_char_p
     lib.heget_shutdown.restype = None
     for f in EXPORTS[:-2]:
@@ -370,3 +371,10 @@ def shutdown() -> None:
 
 def lib():
     return _lib
+
+
+def valu_peak() -> dict:
+    """Measured FP32 and FP64 FMA ceilings of the device (TFLOP/s)."""
+    f32, f64 = C.c_double(0.0), C.c_double(0.0)
+    _check(_lib.heget_valu_peak(C.byref(f32), C.byref(f64)), "heget_valu_peak")
+    return {"fp32_tflops": f32.value, "fp64_tflops": f64.value}

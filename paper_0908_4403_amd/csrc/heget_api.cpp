@@ -1281,6 +1281,43 @@ heget_status heget_me2_flops(int n, heget_prec prec, double *flops_per_point, he
     return HEGET_OK;
 }
 
+heget_status heget_valu_peak(double *fp32_tflops, double *fp64_tflops)
+{
+    g_err.clear();
+    std::lock_guard<std::mutex> lk(g_mu);
+    HG_TRY(ensure_device());
+    hipStream_t s = g.stream;
+    int cus = 0;
+    HG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g.device));
+    const int blocks = cus * 16;  // 16 waves per CU
+    const int iters = 512;
+    HG_TRY(scratch_bind(s));
+    void *out = nullptr;
+    HG_TRY(scratch(S_OUT, size_t(blocks) * 256 * sizeof(double), &out));
+    hipEvent_t e0, e1;
+    HG_HIP(hipEventCreate(&e0));
+    HG_HIP(hipEventCreate(&e1));
+    double *res[2] = {fp64_tflops, fp32_tflops};
+    for (int prec = 0; prec < 2; ++prec) {
+        if (!res[prec]) continue;
+        HG_HIP(heget::launch_fma_peak(prec, out, blocks, iters, s));  // warm-up
+        float best = 0.f;
+        for (int r = 0; r < 3; ++r) {
+            HG_HIP(hipEventRecord(e0, s));
+            HG_HIP(heget::launch_fma_peak(prec, out, blocks, iters, s));
+            HG_HIP(hipEventRecord(e1, s));
+            HG_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (r == 0 || ms < best) best = ms;
+        }
+        *res[prec] = heget::fma_peak_flops(blocks, iters) / (double(best) * 1e-3) / 1e12;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return HEGET_OK;
+}
+
 const char *heget_last_error(void) { return g_err.c_str(); }
 
 void heget_shutdown(void)

@@ -98,6 +98,11 @@ hipError_t launch_sum_chunks(const double *part, int nchunks, int64_t ld, const 
 // and, if `record` is set, the heget_result record for n_gen generated points.
 hipError_t launch_final(const double *partials, const int64_t *d_count, int64_t n_gen, double *res,
                         void *record, hipStream_t stream);
+// FMA issue-rate probe: blocks x 256 threads, iters x 128 FMAs per thread into
+// out[blocks * 256] (float for prec 1, double for prec 0); its flop count.
+hipError_t launch_fma_peak(int prec, void *out, int blocks, int iters, hipStream_t stream);
+double fma_peak_flops(int blocks, int iters);
+
 // Zero a small device buffer with a kernel (usable under stream capture).
 hipError_t launch_zero_u32(unsigned *p, int count, hipStream_t stream);
 

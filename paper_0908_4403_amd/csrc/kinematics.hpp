@@ -12,6 +12,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "fastmath.hpp"
 #include "rng.hpp"
 
 namespace heget {
@@ -32,8 +33,10 @@ __device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t poi
         uniform_pair(seed, point, 2u * i + 1u, 0u, ue1, ue2);
         const double c = 2.0 * ucos - 1.0;
         const double s = sqrt(1.0 - c * c);
+        // the momenta use the library's sincospi and log, so they agree with
+        // any correctly rounded evaluation to an ulp
         double sf, cf;
-        sincospi(2.0 * uphi, &sf, &cf);  // azimuth 2 pi uphi, reduced exactly
+        sincospi(2.0 * uphi, &sf, &cf);  // azimuth 2 pi uphi
         const double e = -log(ue1 * ue2);
         k[i] = {e, e * s * cf, e * s * sf, e * c};
         Qe += k[i].e;
@@ -59,7 +62,10 @@ __device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t poi
 
 // 1 if every photon has pT > pt_min and |eta + y| < eta_max and every pair
 // Delta R > dr_min (bounds <= 0 are off).  eta = atanh(pz/|p|), evaluated as
-// sign(pz) log((|p| + |pz|) / pT), which has no cancellation near the beam.
+// sign(pz) log((|p| + |pz|) / pT), which has no cancellation near the beam;
+// phi = atan2(py, px).  Both with the short functions of fastmath.hpp: they
+// only decide cuts, and a decision can move only for a point within a few
+// ulp of a bound.
 template <int N>
 __device__ __forceinline__ bool pass_cuts(const Vec4 (&k)[N], double y, double pt_min,
                                           double eta_max, double dr_min)
@@ -71,8 +77,8 @@ __device__ __forceinline__ bool pass_cuts(const Vec4 (&k)[N], double y, double p
         const double pt2 = k[i].x * k[i].x + k[i].y * k[i].y;
         const double pt = sqrt(pt2);
         const double pabs = sqrt(pt2 + k[i].z * k[i].z);
-        eta[i] = copysign(log((pabs + fabs(k[i].z)) / pt), k[i].z) + y;
-        phi[i] = atan2(k[i].y, k[i].x);
+        eta[i] = copysign(fm::log((pabs + fabs(k[i].z)) / pt), k[i].z) + y;
+        phi[i] = fm::atan2(k[i].y, k[i].x);
         if (pt_min > 0.0) ok = ok && (pt > pt_min);
         if (eta_max > 0.0) ok = ok && (fabs(eta[i]) < eta_max);
     }
