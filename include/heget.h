@@ -86,6 +86,12 @@ typedef struct {
     double sqrt_shat_lo, sqrt_shat_hi; /* UNIFORM: range; PP: lo = min sqrt(shat) */
     heget_cuts cuts;
     double alpha, charge; /* e^2 = 4 pi alpha; quark charge in units of e */
+    int32_t helicity_sampling; /* 0: sum all helicities (eq. (2)); 1: one helicity
+                                * configuration per point, drawn uniformly from the
+                                * 2^(n+1) non-vanishing ones and weighted by 2^(n+1)
+                                * (the paper's per-event helicities, Section 3.1);
+                                * heget_xsec only, not heget_xsec_batch */
+    int32_t reserved;          /* set to 0 */
 } heget_config;
 
 typedef struct {
@@ -145,6 +151,22 @@ heget_status heget_xsec_async(int n, const heget_config *cfg, heget_result *out,
  * Non-finite weights are not reported in the status (check d_out->sigma_fb). */
 heget_status heget_xsec_device(int n, const heget_config *cfg, heget_result *d_out,
                                heget_stream stream);
+
+/* Event observables for heget_xsec_hist (the distributions of Fig. 2). */
+typedef enum {
+    HEGET_OBS_PT_MAX = 0, /* largest photon pT [GeV] */
+    HEGET_OBS_DR_MIN = 1  /* smallest Delta R over photon pairs (eq. (10)) */
+} heget_observable;
+
+/* heget_xsec plus a weighted histogram of one observable over the same
+ * points: hist[0] = underflow (< lo), hist[1 + b] = bin b of nbins equal bins
+ * on [lo, hi), hist[nbins + 1] = overflow (host, [nbins + 2]), each the sum of
+ * the weights in it over n_gen (fb per bin; the entries add up to sigma).
+ * The bins are summed as 64-bit fixed-point integers scaled from the total
+ * weight, so they are exact to 2^-62 of sigma and independent of the order of
+ * the device's atomic adds.  1 <= nbins <= 4096, finite lo < hi. */
+heget_status heget_xsec_hist(int n, const heget_config *cfg, int observable, int nbins, double lo,
+                             double hi, double *hist, heget_result *out);
 
 /* Several cross sections in one device pass (e.g. n = 2..7 with different
  * point counts), captured on first use as ONE hipGraph that later calls with

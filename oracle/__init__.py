@@ -29,7 +29,8 @@ class OrcConfig(C.Structure):
                 ("first_point", C.c_int64), ("sqrt_s", C.c_double),
                 ("sqrt_shat_lo", C.c_double), ("sqrt_shat_hi", C.c_double),
                 ("pt_min", C.c_double), ("eta_max", C.c_double), ("dr_min", C.c_double),
-                ("alpha", C.c_double), ("charge", C.c_double), ("me2_method", C.c_int)]
+                ("alpha", C.c_double), ("charge", C.c_double), ("me2_method", C.c_int),
+                ("helicity_sampling", C.c_int)]
 
 
 class OrcResult(C.Structure):
@@ -76,6 +77,11 @@ def lib():
         L.orc_point.argtypes = [C.c_int, C.POINTER(OrcConfig), C.c_uint64, _dp, _dp, _dp, _dp]
         L.orc_point.restype = C.c_int
         L.orc_xsec.argtypes = [C.c_int, C.POINTER(OrcConfig), C.POINTER(OrcResult), _dp]
+        L.orc_draw_helicity.argtypes = [C.c_int, C.c_uint64, C.c_uint64, _ip, _ip, _ip]
+        L.orc_observable.argtypes = [C.c_int, _dp, C.c_int]
+        L.orc_observable.restype = C.c_double
+        L.orc_hist.argtypes = [C.c_int, C.POINTER(OrcConfig), C.c_int, C.c_int, C.c_double,
+                               C.c_double, _dp]
         L.orc_xsec.restype = C.c_int
         L.orc_gev2_fb.restype = C.c_double
         _LIB = L
@@ -159,6 +165,14 @@ def amp(p, h1: int, h2: int, lam, g: float | None = None, u_along_minus_z: bool 
     return complex(re.value, im.value)
 
 
+def draw_helicity(n: int, seed: int, point: int):
+    """(h_u, h_ubar, lam[n]) drawn for `point` in helicity-sampling mode."""
+    h1, h2 = C.c_int(), C.c_int()
+    lam = np.zeros(8, dtype=np.int32)
+    lib().orc_draw_helicity(n, seed, point, C.byref(h1), C.byref(h2), lam.ctypes.data_as(_ip))
+    return h1.value, h2.value, tuple(int(x) for x in lam[:n])
+
+
 def amp_from_u(p, h1: int, h2: int, lam, g: float | None = None) -> complex:
     p = _f64(p)
     n = p.shape[0] - 2
@@ -237,11 +251,13 @@ class Config:
     alpha: float = ALPHA
     charge: float = CHARGE_U
     me2_method: int = 0  # 0: ordering sum, 1: subset recursion
+    helicity_sampling: int = 0  # 1: one drawn helicity configuration per point
 
     def c(self) -> OrcConfig:
         return OrcConfig(self.mode, self.seed, self.npoints, self.first_point, self.sqrt_s,
                          self.sqrt_shat_lo, self.sqrt_shat_hi, self.pt_min, self.eta_max,
-                         self.dr_min, self.alpha, self.charge, self.me2_method)
+                         self.dr_min, self.alpha, self.charge, self.me2_method,
+                         self.helicity_sampling)
 
 
 def point(n: int, cfg: Config, i: int):
@@ -268,3 +284,20 @@ def xsec(n: int, cfg: Config, want_weights: bool = False):
 
 def gev2_fb() -> float:
     return lib().orc_gev2_fb()
+
+
+PT_MAX, DR_MIN = 0, 1
+
+
+def observable(photons, which: int) -> float:
+    """Largest photon pT (which = 0) or smallest photon-pair Delta R (1)."""
+    k = _f64(photons)
+    return lib().orc_observable(k.shape[0], _ptr(k), which)
+
+
+def hist(n: int, cfg: Config, which: int, nbins: int, lo: float, hi: float) -> np.ndarray:
+    """[underflow, nbins bins on [lo, hi), overflow] of sum(w)/N per bin (fb)."""
+    out = np.zeros(nbins + 2)
+    c = cfg.c()
+    lib().orc_hist(n, C.byref(c), which, nbins, lo, hi, _ptr(out))
+    return out

@@ -590,8 +590,32 @@ static double partonic_factor(int n, double shat)
            orc_rambo_weight(n, shat) * orc_gev2_fb();
 }
 
-static double point_me2(int n, const orc_config *cfg, const double *p, int u_minus_z)
+void orc_draw_helicity(int n, uint64_t seed, uint64_t point, int *h1, int *h2, int *lam)
 {
+    const uint32_t ctr[4] = {(uint32_t)point, (uint32_t)(point >> 32), 0u, 2u};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    const uint32_t w = out[0];
+    *h1 = (w & 1u) ? 1 : -1;
+    *h2 = -*h1;
+    for (int i = 0; i < n; ++i) lam[i] = ((w >> (1 + i)) & 1u) ? 1 : -1;
+}
+
+/* |M|^2 of the point: the helicity sum, or in sampling mode the estimator
+ * 2^(n+1) |M_h|^2 of the drawn configuration (its mean over the uniform draw
+ * is the sum over the 2^(n+1) non-vanishing configurations). */
+static double point_me2(int n, const orc_config *cfg, const double *p, int u_minus_z,
+                        uint64_t point)
+{
+    if (cfg->helicity_sampling) {
+        int h1, h2, lam[8];
+        orc_draw_helicity(n, cfg->seed, point, &h1, &h2, lam);
+        const double g = -sqrt(4.0 * M_PI * cfg->alpha) * cfg->charge;
+        double re, im;
+        orc_amp(n, p, h1, h2, lam, g, u_minus_z, &re, &im);
+        return ldexp(re * re + im * im, n + 1);
+    }
     if (cfg->me2_method == 1 && !u_minus_z) return orc_me2_subsets(n, p, cfg->alpha, cfg->charge);
     return orc_me2(n, p, cfg->alpha, cfg->charge, 1, u_minus_z);
 }
@@ -628,7 +652,7 @@ int orc_point(int n, const orc_config *cfg, uint64_t point, double *p, double *y
     double base = partonic_factor(n, shat);
     if (cfg->mode != ORC_PP_TOY) {
         if (!orc_pass_cuts(n, p + 8, 0.0, cfg->pt_min, cfg->eta_max, cfg->dr_min)) return 0;
-        *me2 = point_me2(n, cfg, p, 0);
+        *me2 = point_me2(n, cfg, p, 0, point);
         *w = base * *me2;
         return 1;
     }
@@ -648,11 +672,78 @@ int orc_point(int n, const orc_config *cfg, uint64_t point, double *p, double *y
     }
     int passA = orc_pass_cuts(n, p + 8, yA, cfg->pt_min, cfg->eta_max, cfg->dr_min);
     int passB = orc_pass_cuts(n, pB + 8, yB, cfg->pt_min, cfg->eta_max, cfg->dr_min);
-    double meA = passA ? point_me2(n, cfg, p, 0) : 0.0;
-    double meB = passB ? point_me2(n, cfg, pB, 1) : 0.0;
+    double meA = passA ? point_me2(n, cfg, p, 0, point) : 0.0;
+    double meB = passB ? point_me2(n, cfg, pB, 1, point) : 0.0;
     *me2 = passA ? meA : meB;
     *w = fpdf * base * (meA + meB);
     return passA || passB;
+}
+
+double orc_observable(int n, const double *k, int observable)
+{
+    if (observable == 0) {
+        double m = 0.0;
+        for (int i = 0; i < n; ++i) m = fmax(m, hypot(k[4 * i + 1], k[4 * i + 2]));
+        return m;
+    }
+    double eta[8], phi[8], m = INFINITY;
+    for (int i = 0; i < n; ++i) {
+        const double *q = k + 4 * i;
+        eta[i] = atanh(q[3] / sqrt(q[1] * q[1] + q[2] * q[2] + q[3] * q[3]));
+        phi[i] = atan2(q[2], q[1]);
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            double dphi = fabs(phi[i] - phi[j]);
+            if (dphi > M_PI) dphi = 2.0 * M_PI - dphi;
+            m = fmin(m, hypot(eta[i] - eta[j], dphi));
+        }
+    return m;
+}
+
+int orc_hist(int n, const orc_config *cfg, int observable, int nbins, double lo, double hi,
+             double *hist)
+{
+    init_gamma();
+    const int64_t N = cfg->npoints;
+    double *w = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    double *x = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    int threads = 1;
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+#pragma omp single
+        threads = omp_get_num_threads();
+#endif
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < N; ++i) {
+            double p[40], y, me2;
+            orc_point(n, cfg, (uint64_t)(cfg->first_point + i), p, &y, &me2, &w[i]);
+            x[i] = orc_observable(n, p + 8, observable);
+        }
+    }
+    double *s = (double *)calloc((size_t)nbins + 2, sizeof(double));
+    double *c = (double *)calloc((size_t)nbins + 2, sizeof(double));
+    for (int64_t i = 0; i < N; ++i) {
+        if (w[i] == 0.0) continue;
+        int b;
+        if (x[i] < lo) b = 0;
+        else if (x[i] >= hi) b = nbins + 1;
+        else {
+            b = 1 + (int)((x[i] - lo) / (hi - lo) * nbins);
+            if (b > nbins) b = nbins;
+        }
+        const double t = s[b] + w[i];
+        if (fabs(s[b]) >= fabs(w[i])) c[b] += (s[b] - t) + w[i];
+        else c[b] += (w[i] - t) + s[b];
+        s[b] = t;
+    }
+    for (int b = 0; b < nbins + 2; ++b) hist[b] = N > 0 ? (s[b] + c[b]) / (double)N : 0.0;
+    free(s);
+    free(c);
+    free(w);
+    free(x);
+    return threads;
 }
 
 int orc_xsec(int n, const orc_config *cfg, orc_result *out, double *w_out)

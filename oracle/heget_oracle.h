@@ -109,6 +109,7 @@ typedef struct {
     double pt_min, eta_max, dr_min;
     double alpha, charge;
     int me2_method;      /* 0: sum over orderings (orc_me2); 1: subset recursion */
+    int helicity_sampling; /* 1: one helicity configuration per point (see orc_point) */
 } orc_config;
 
 typedef struct {
@@ -118,11 +119,34 @@ typedef struct {
 
 /* Per-point weight w (fb) of point `point` (0 if cut or below threshold),
  * and its event: p[n+2][4] in the partonic CM frame (u along +z), the boost
- * rapidity y to the lab and the |M|^2 used.  Returns 1 if accepted. */
+ * rapidity y to the lab and the |M|^2 used.  Returns 1 if accepted.
+ * With helicity_sampling the |M|^2 used is the estimator 2^(n+1) |M_h|^2 of
+ * the one configuration h drawn by orc_draw_helicity for the point. */
 int orc_point(int n, const orc_config *cfg, uint64_t point, double *p, double *y,
               double *me2, double *w);
 /* OpenMP over points, then a fixed-order Neumaier sum; returns threads used. */
 int orc_xsec(int n, const orc_config *cfg, orc_result *out, double *w_out);
+
+/* The helicity configuration point `point` draws in sampling mode (the
+ * paper's per-event helicities, Section 3.1): word 0 of Philox4x32-10 at
+ * counter {lo(point), hi(point), 0, 2}, key = seed.  Bit 0 picks the quark
+ * pair (0: h_u = -1, h_ubar = +1; 1: h_u = +1, h_ubar = -1), bit 1 + i the
+ * helicity of photon i (1: +1).  These are the 2^(n+1) configurations with a
+ * non-vanishing amplitude, drawn uniformly. */
+void orc_draw_helicity(int n, uint64_t seed, uint64_t point, int *h1, int *h2, int *lam);
+
+/* Event observables of Fig. 2 (photons k[n][4]): 0 = largest photon pT
+ * (GeV); 1 = smallest Delta R over photon pairs (Delta phi folded into
+ * [0, pi]; both are unchanged by the longitudinal boost to the lab). */
+double orc_observable(int n, const double *k, int observable);
+
+/* Weighted histogram of an observable: hist[0] = underflow (< lo), hist[1 +
+ * b] = bin b of nbins equal bins on [lo, hi), hist[nbins + 1] = overflow,
+ * each the sum of w over the points in it divided by N (fb per bin; the
+ * entries add up to sigma).  Same points and weights as orc_xsec; the sums
+ * are Neumaier sums in point order.  Returns the threads used. */
+int orc_hist(int n, const orc_config *cfg, int observable, int nbins, double lo, double hi,
+             double *hist);
 
 /* (hbar c)^2 in GeV^2 fb */
 double orc_gev2_fb(void);

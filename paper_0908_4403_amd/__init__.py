@@ -34,9 +34,11 @@ OK, WARN_NONFINITE = 0, 1
 ERR_ARG, ERR_RANGE, ERR_ALLOC, ERR_DEVICE = -1, -2, -3, -4
 FP64, FP32 = 0, 1
 FIXED_SHAT, UNIFORM_SQRTSHAT, PP_TOY = 0, 1, 2
+OBS_PT_MAX, OBS_DR_MIN = 0, 1
 
 EXPORTS = ["heget_gen_points", "heget_gen_points_device", "heget_me2", "heget_me2_device",
-           "heget_xsec", "heget_xsec_async", "heget_xsec_device", "heget_xsec_batch",
+           "heget_xsec", "heget_xsec_async", "heget_xsec_device", "heget_xsec_hist",
+           "heget_xsec_batch",
            "heget_set_batch_schedule", "heget_batch_schedule_in_use",
            "heget_set_couplings",
            "heget_timing_enable",
@@ -53,7 +55,7 @@ class _Config(C.Structure):
     _fields_ = [("mode", C.c_int32), ("prec", C.c_int32), ("seed", C.c_uint64),
                 ("npoints", C.c_int64), ("sqrt_s", C.c_double), ("sqrt_shat_lo", C.c_double),
                 ("sqrt_shat_hi", C.c_double), ("cuts", Cuts), ("alpha", C.c_double),
-                ("charge", C.c_double)]
+                ("charge", C.c_double), ("helicity_sampling", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Shape(C.Structure):
@@ -97,6 +99,8 @@ def _load():
     lib.heget_xsec.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result)]
     lib.heget_xsec_async.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result), C.c_void_p]
     lib.heget_set_batch_schedule.argtypes = [C.c_int]
+    lib.heget_xsec_hist.argtypes = [C.c_int, C.POINTER(_Config), C.c_int, C.c_int, C.c_double,
+                                    C.c_double, _dp, C.POINTER(Result)]
     lib.heget_batch_schedule_in_use.argtypes = [C.POINTER(C.c_int), C.POINTER(_Config), C.c_int,
                                                 C.POINTER(C.c_int)]
     lib.heget_xsec_device.argtypes = [C.c_int, C.POINTER(_Config), C.c_void_p, C.c_void_p]
@@ -201,11 +205,13 @@ class Config:
     dr_min: float = 0.4
     alpha: float = 1.0 / 137.0
     charge: float = 2.0 / 3.0
+    helicity_sampling: int = 0  # 1: one drawn helicity configuration per point
 
     def c(self) -> _Config:
         return _Config(self.mode, self.prec, self.seed, self.npoints, self.sqrt_s,
                        self.sqrt_shat_lo, self.sqrt_shat_hi,
-                       Cuts(self.pt_min, self.eta_max, self.dr_min), self.alpha, self.charge)
+                       Cuts(self.pt_min, self.eta_max, self.dr_min), self.alpha, self.charge,
+                       self.helicity_sampling, 0)
 
 
 def xsec(n: int, cfg: Config, return_status: bool = False) -> dict:
@@ -378,3 +384,14 @@ def valu_peak() -> dict:
     f32, f64 = C.c_double(0.0), C.c_double(0.0)
     _check(_lib.heget_valu_peak(C.byref(f32), C.byref(f64)), "heget_valu_peak")
     return {"fp32_tflops": f32.value, "fp64_tflops": f64.value}
+
+
+def xsec_hist(n: int, cfg: Config, observable: int, nbins: int, lo: float, hi: float):
+    """(hist[nbins + 2] = [underflow, bins on [lo, hi), overflow] in fb per bin,
+    result dict) for the observable over the points of heget_xsec."""
+    h = np.zeros(nbins + 2)
+    r = Result()
+    c = cfg.c()
+    _check(_lib.heget_xsec_hist(n, C.byref(c), observable, nbins, lo, hi, _ptr(h), C.byref(r)),
+           "heget_xsec_hist")
+    return h, r.as_dict()

@@ -87,7 +87,7 @@ constexpr int kRing = 256;
 
 enum Slot {
     S_MOM, S_WFAC, S_FLAG, S_BCOUNT, S_OFFS, S_COUNT, S_INDEX, S_PART, S_PARTIALS, S_RES, S_FLAGS,
-    S_OUT, S_BATCH, S_NSLOTS
+    S_OUT, S_BATCH, S_HEL, S_WOUT, S_BINS, S_HIST, S_NSLOTS
 };
 
 // Captured mixed-n batches, keyed by their configuration; replayed on repeat calls.
@@ -491,12 +491,12 @@ heget_status me2_on_device(int n, int64_t np, const double *d_mom, double *d_out
     const int nchunks = plan_chunks(*v, np);
     double *part = d_out;
     if (nchunks > 1) HG_TRY(scratch_t<double>(S_PART, size_t(nchunks) * size_t(np), &part));
-    heget::Me2Args a{d_mom, np, nullptr, nullptr, np, nchunks, me2_coef(n, g_alpha, g_charge),
-                     part, np, nullptr, nullptr, d_flags};
+    heget::Me2Args a{d_mom, np, nullptr, nullptr, nullptr, np, nchunks,
+                     me2_coef(n, g_alpha, g_charge), part, np, nullptr, nullptr, nullptr, d_flags};
     HG_TRY(launch_me2_timed(*v, a, s));
     if (nchunks > 1)
         HG_HIP(heget::launch_sum_chunks(part, nchunks, np, nullptr, np, d_out, nullptr, nullptr,
-                                        nullptr, d_flags, s));
+                                        nullptr, nullptr, d_flags, s));
     return HEGET_OK;
 }
 
@@ -509,6 +509,8 @@ heget_status check_config(int n, const heget_config *cfg)
     HG_TRY(check_cuts(&cfg->cuts));
     if (!(std::isfinite(cfg->alpha) && cfg->alpha > 0.0 && std::isfinite(cfg->charge)))
         return fail(HEGET_ERR_ARG, "alpha must be > 0 and charge finite");
+    if (cfg->helicity_sampling != 0 && cfg->helicity_sampling != 1)
+        return fail(HEGET_ERR_ARG, "helicity_sampling must be 0 or 1");
     switch (cfg->mode) {
     case HEGET_FIXED_SHAT: HG_TRY(check_energy(cfg->sqrt_s, "sqrt_s")); break;
     case HEGET_UNIFORM_SQRTSHAT:
@@ -548,6 +550,8 @@ struct McBufs {
     double *mom, *wfac, *part, *partials, *res;
     uint8_t *flag;
     int32_t *bcount, *offs, *index;
+    uint16_t *hel;  // sampled helicity configurations, or nullptr (helicity sum)
+    double *wout;   // per-survivor weights (histograms), or nullptr
     int64_t *d_count;
     int nchunks;
 };
@@ -589,6 +593,7 @@ heget_status enqueue_generation(int n, const heget_config &c, const McBufs &b, h
     const int64_t np = c.npoints;
     heget::GenParams gp = slice_gen_params(n, c);
     gp.clear_word = clear;
+    gp.hel_out = b.hel;
     HG_HIP(heget::launch_gen(n, gp, b.mom, np, b.wfac, b.flag, b.bcount, s));
     HG_HIP(heget::launch_scan(b.bcount, static_cast<int>((np + 255) / 256), b.offs, b.d_count, s));
     HG_HIP(heget::launch_compact(b.flag, np, b.offs, b.index, s));
@@ -604,30 +609,44 @@ heget_status enqueue_reduction(const heget_config &c, const McBufs &b, unsigned 
     const int64_t np = c.npoints;
     if (b.nchunks > 1 || !weighted_in_me2)
         HG_HIP(heget::launch_sum_chunks(b.part, b.nchunks, np, b.d_count, np, nullptr, b.index,
-                                        b.wfac, b.partials, flags, s));
+                                        b.wfac, b.partials, b.wout, flags, s));
     HG_HIP(heget::launch_final(b.partials, b.d_count, np, b.res, record, s));
     return HEGET_OK;
 }
 
+// Arguments of the amplitude pass of a Monte-Carlo call.  With helicity
+// sampling the per-point value is the estimator 2^(n+1) |M_h|^2 of the drawn
+// configuration: 2^n times the kernel's two-block coefficient.
 heget::Me2Args mc_me2_args(int n, const heget_config &c, const McBufs &b, unsigned *flags)
 {
-    return heget::Me2Args{b.mom, c.npoints, b.index, b.d_count, c.npoints, b.nchunks,
-                          me2_coef(n, c.alpha, c.charge), b.part, c.npoints, b.wfac,
-                          b.nchunks == 1 ? b.partials : nullptr, flags};
+    const double coef = me2_coef(n, c.alpha, c.charge) * (b.hel ? double(1 << n) : 1.0);
+    const bool epi = b.nchunks == 1;
+    return heget::Me2Args{b.mom,      c.npoints,  b.index,  b.hel,  b.d_count,
+                          c.npoints,  b.nchunks,  coef,     b.part, c.npoints,
+                          b.wfac,     epi ? b.partials : nullptr, epi ? b.wout : nullptr, flags};
 }
+
+// A weighted histogram to fill beside the cross section (heget_xsec_hist).
+struct HistReq {
+    int observable, nbins;
+    double lo, hi;
+    double *host;  // [nbins + 2], written by a copy enqueued on the stream
+};
 
 // Enqueue the whole path.  The result goes to d_out (device-writable, filled by
 // a kernel) when given, else to *out through the pinned ring and a host callback.
 heget_status xsec_enqueue(int n, const heget_config *cfg, heget_result *out, heget_result *d_out,
-                          hipStream_t s, unsigned **flags_out)
+                          hipStream_t s, unsigned **flags_out, const HistReq *hist = nullptr)
 {
     const int64_t np = cfg->npoints;
-    const heget::Me2Variant *v = pick_variant(cfg->prec, n);
+    const bool sampled = cfg->helicity_sampling != 0;
+    const heget::Me2Variant *v =
+        sampled ? heget::me2_sampled(cfg->prec, n) : pick_variant(cfg->prec, n);
     if (!v) return fail(HEGET_ERR_ARG, "no compiled amplitude kernel for this n/precision");
 
     const int64_t nb = (np + 255) / 256;
     McBufs b{};
-    b.nchunks = plan_chunks(*v, np / 2);
+    b.nchunks = sampled ? 1 : plan_chunks(*v, np / 2);
     unsigned *flags;
     HG_TRY(scratch_bind(s));
     HG_TRY(scratch_t<double>(S_MOM, size_t(n + 2) * 4 * size_t(np), &b.mom));
@@ -637,6 +656,16 @@ heget_status xsec_enqueue(int n, const heget_config *cfg, heget_result *out, heg
     HG_TRY(scratch_t<int32_t>(S_OFFS, size_t(nb), &b.offs));
     HG_TRY(scratch_t<int64_t>(S_COUNT, 1, &b.d_count));
     HG_TRY(scratch_t<int32_t>(S_INDEX, size_t(np), &b.index));
+    b.hel = nullptr;
+    if (sampled) HG_TRY(scratch_t<uint16_t>(S_HEL, size_t(np), &b.hel));
+    b.wout = nullptr;
+    unsigned long long *bins = nullptr;
+    double *d_hist = nullptr;
+    if (hist) {
+        HG_TRY(scratch_t<double>(S_WOUT, size_t(np), &b.wout));
+        HG_TRY(scratch_t<unsigned long long>(S_BINS, size_t(hist->nbins) + 2, &bins));
+        HG_TRY(scratch_t<double>(S_HIST, size_t(hist->nbins) + 2, &d_hist));
+    }
     b.part = nullptr;
     if (b.nchunks > 1) HG_TRY(scratch_t<double>(S_PART, size_t(b.nchunks) * size_t(np), &b.part));
     HG_TRY(scratch_t<double>(S_PARTIALS, size_t(3) * size_t((np + 63) / 64), &b.partials));
@@ -646,6 +675,14 @@ heget_status xsec_enqueue(int n, const heget_config *cfg, heget_result *out, heg
     HG_TRY(enqueue_generation(n, *cfg, b, s, flags));  // also clears flags
     HG_TRY(launch_me2_timed(*v, mc_me2_args(n, *cfg, b, flags), s));
     HG_TRY(enqueue_reduction(*cfg, b, flags, d_out, s));
+    if (hist) {
+        HG_HIP(heget::launch_zero_u32(reinterpret_cast<unsigned *>(bins), 2 * (hist->nbins + 2), s));
+        HG_HIP(heget::launch_hist(n, b.mom, np, b.index, b.wout, b.d_count, np, b.res,
+                                  hist->observable, hist->nbins, hist->lo, hist->hi, bins, s));
+        HG_HIP(heget::launch_hist_finish(bins, hist->nbins, b.res, np, d_hist, s));
+        HG_HIP(hipMemcpyAsync(hist->host, d_hist, sizeof(double) * size_t(hist->nbins + 2),
+                              hipMemcpyDeviceToHost, s));
+    }
     if (!d_out) {
         const unsigned slot = g.ring.fetch_add(1) % kRing;
         double *staged = g.pinned + 8 * slot;
@@ -704,6 +741,8 @@ void carve_batch(Arena &ar, int ncfg, const int *n, const heget_config *cfgs, in
         b.bcount = ar.take<int32_t>(size_t((np + 255) / 256));
         b.offs = ar.take<int32_t>(size_t((np + 255) / 256));
         b.index = ar.take<int32_t>(size_t(np));
+        b.hel = nullptr;
+        b.wout = nullptr;
         b.d_count = ar.take<int64_t>(1);
         // the persistent kernel always writes |M|^2 per chunk
         const bool need_part = b.nchunks > 1 || schedule == 1;
@@ -1037,6 +1076,34 @@ heget_status heget_xsec(int n, const heget_config *cfg, heget_result *out)
     return mc_flags_status(flags);
 }
 
+heget_status heget_xsec_hist(int n, const heget_config *cfg, int observable, int nbins, double lo,
+                             double hi, double *hist, heget_result *out)
+{
+    g_err.clear();
+    HG_TRY(check_config(n, cfg));
+    if (!out || !hist) return fail(HEGET_ERR_ARG, "out and hist must not be NULL");
+    if (observable != HEGET_OBS_PT_MAX && observable != HEGET_OBS_DR_MIN)
+        return fail(HEGET_ERR_ARG, "unknown observable");
+    if (nbins < 1 || nbins > heget::kHistMaxBins)
+        return fail(HEGET_ERR_RANGE, "nbins must be in 1..4096");
+    if (!(std::isfinite(lo) && std::isfinite(hi) && lo < hi))
+        return fail(HEGET_ERR_ARG, "need finite lo < hi");
+    if (cfg->npoints == 0) {
+        *out = heget_result{};
+        for (int b = 0; b < nbins + 2; ++b) hist[b] = 0.0;
+        return HEGET_OK;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    HG_TRY(ensure_device());
+    unsigned *d_flags = nullptr;
+    const HistReq req{observable, nbins, lo, hi, hist};
+    HG_TRY(xsec_enqueue(n, cfg, out, nullptr, g.stream, &d_flags, &req));
+    unsigned flags = 0;
+    HG_HIP(hipMemcpyAsync(&flags, d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, g.stream));
+    HG_HIP(hipStreamSynchronize(g.stream));
+    return mc_flags_status(flags);
+}
+
 heget_status heget_set_batch_schedule(int schedule)
 {
     g_err.clear();
@@ -1056,6 +1123,8 @@ heget_status heget_xsec_batch(const int *n, const heget_config *cfgs, int ncfg,
         return fail(HEGET_ERR_RANGE, "ncfg must be in 1..8");
     for (int i = 0; i < ncfg; ++i) {
         HG_TRY(check_config(n[i], &cfgs[i]));
+        if (cfgs[i].helicity_sampling)
+            return fail(HEGET_ERR_ARG, "helicity sampling is not available in batches");
         if (cfgs[i].prec != cfgs[0].prec)
             return fail(HEGET_ERR_ARG, "all configurations of a batch need the same prec");
     }
@@ -1166,8 +1235,9 @@ heget_status heget_autotune(int n, heget_prec prec, int64_t npoints, heget_shape
         const int nchunks = plan_chunks(v, npoints);
         double *out = nullptr;
         HG_TRY(scratch_t<double>(S_OUT, size_t(nchunks) * size_t(npoints), &out));
-        heget::Me2Args a{d_mom, npoints, nullptr, nullptr, npoints, nchunks,
-                         me2_coef(n, g_alpha, g_charge), out, npoints, nullptr, nullptr, d_flags};
+        heget::Me2Args a{d_mom, npoints, nullptr, nullptr, nullptr, npoints, nchunks,
+                         me2_coef(n, g_alpha, g_charge), out, npoints, nullptr, nullptr, nullptr,
+                         d_flags};
         HG_HIP(heget::launch_me2(v, a, s));  // warm-up
         HG_HIP(hipEventRecord(e0, s));
         const int reps = 3;

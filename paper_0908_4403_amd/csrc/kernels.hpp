@@ -22,12 +22,15 @@ struct Me2Variant {
 // All compiled variants (static table) and the default choice per (prec, n).
 const Me2Variant *me2_variants(int *count);
 const Me2Variant *me2_default(int prec, int n);
+// The helicity-sampling kernel (h = 0) for (prec, n).
+const Me2Variant *me2_sampled(int prec, int n);
 
 // Arguments of one amplitude launch.
 struct Me2Args {
     const double *mom;       // SoA [(n+2)*4][ld]
     int64_t ld;
     const int32_t *index;    // survivor -> column of mom (and of wfac), or nullptr (identity)
+    const uint16_t *hel;     // sampled helicity configuration per column (H = 0 shapes only)
     const int64_t *d_count;  // number of points on the device, or nullptr
     int64_t count;           // number of points when d_count is null; else an upper bound
     int nchunks;             // helicity chunks (each a separate work item)
@@ -36,6 +39,7 @@ struct Me2Args {
     int64_t ld_out;
     const double *wfac;      // per-point weight factor (with partials), else nullptr
     double *partials;        // one chunk: per-tile weighted triples instead of out
+    double *wout;            // with partials: also each point's weight, or nullptr
     unsigned *flags;         // bit 0 set if a result is not finite
 };
 
@@ -92,7 +96,22 @@ hipError_t launch_compact(const uint8_t *flag, int64_t np, const int32_t *offset
 // amplitude kernel's one-chunk epilogue).
 hipError_t launch_sum_chunks(const double *part, int nchunks, int64_t ld, const int64_t *d_count,
                              int64_t count, double *out, const int32_t *index, const double *wfac,
-                             double *partials, unsigned *flags, hipStream_t stream);
+                             double *partials, double *wout, unsigned *flags, hipStream_t stream);
+
+// Weighted histograms of an event observable (0: largest photon pT, 1:
+// smallest photon-pair Delta R) over the survivors: w[k] of survivor k (point
+// index[k] of mom) goes to bins[0] below lo, bins[1 + b] for bin b of nbins on
+// [lo, hi), bins[nbins + 1] above.  Bins are 64-bit fixed-point integers
+// scaled by 2^(62 - e) where 2^e > res[0] (the sum of all weights), so the sums
+// are exact and independent of the order of the atomic adds; `bins` must be
+// zero at launch.  hist_finish converts them to sum(w) / n_gen per bin.
+constexpr int kHistMaxBins = 4096;
+hipError_t launch_hist(int n, const double *mom, int64_t ld, const int32_t *index, const double *w,
+                       const int64_t *d_count, int64_t max_count, const double *res,
+                       int observable, int nbins, double lo, double hi, unsigned long long *bins,
+                       hipStream_t stream);
+hipError_t launch_hist_finish(const unsigned long long *bins, int nbins, const double *res,
+                              int64_t n_gen, double *hist, hipStream_t stream);
 // Fixed-order compensated reduction of the ceil(*d_count / 64) tile triples
 // into res[0..3] = (sum + compensation, compensation, sum of squares, *d_count)
 // and, if `record` is set, the heget_result record for n_gen generated points.

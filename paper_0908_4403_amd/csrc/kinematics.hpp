@@ -111,7 +111,26 @@ struct GenParams {
     double phase_volume_coef;
     int weight_kind;     // 0: write Phi_n (or 0 if cut); 1: write the full non-|M|^2 weight
     unsigned *clear_word;  // if set, zeroed by the generation launch (the call's status flags)
+    uint16_t *hel_out;     // if set, the sampled helicity configuration of every point
 };
+
+// Helicity configuration drawn for `point` in sampling mode (the paper's
+// per-event helicities, Section 3.1): word 0 of the generator at block 0 of
+// stream 2.  Bit 0 picks the quark pair (0: h_u = -1, h_ubar = +1, the pair
+// the amplitude kernel evaluates; 1: its parity image), bit 1 + j the
+// helicity of photon j (1: +1).  Returned in the amplitude kernel's
+// convention: photon bits of the evaluated pair, flipped for the parity image
+// (|M(-h, -lam)| = |M(h, lam)|).
+template <int N>
+__device__ __forceinline__ uint16_t draw_helicity(uint64_t seed, uint64_t point)
+{
+    const Words4 r = philox4x32_10(static_cast<uint32_t>(point), static_cast<uint32_t>(point >> 32),
+                                   0u, 2u, static_cast<uint32_t>(seed),
+                                   static_cast<uint32_t>(seed >> 32));
+    const uint32_t mask = (1u << N) - 1u;
+    const uint32_t lam = (r.w0 >> 1) & mask;
+    return static_cast<uint16_t>((r.w0 & 1u) ? (~lam & mask) : lam);
+}
 
 struct PointKin {
     double sqrt_shat;

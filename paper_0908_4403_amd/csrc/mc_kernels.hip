@@ -70,6 +70,7 @@ gen_kernel(GenParams g, double *__restrict__ mom, int64_t ld, double *__restrict
         store_point<N>(mom, ld, i, e, k);
         wout[i] = acc ? w : 0.0;
         if (flag) flag[i] = acc ? 1 : 0;
+        if (g.hel_out) g.hel_out[i] = draw_helicity<N>(g.seed, static_cast<uint64_t>(g.first + i));
     }
     if (block_count) {
         const int c = __syncthreads_count(acc ? 1 : 0);
@@ -129,7 +130,8 @@ __global__ void __launch_bounds__(256)
 sum_chunks_kernel(const double *__restrict__ part, int nchunks, int64_t ld,
                   const int64_t *__restrict__ d_count, int64_t count, double *__restrict__ out,
                   const int32_t *__restrict__ index, const double *__restrict__ wfac,
-                  double *__restrict__ partials, unsigned *__restrict__ flags)
+                  double *__restrict__ partials, double *__restrict__ wout,
+                  unsigned *__restrict__ flags)
 {
     const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     const int64_t n = d_count ? *d_count : count;
@@ -142,6 +144,7 @@ sum_chunks_kernel(const double *__restrict__ part, int nchunks, int64_t ld,
             for (int c = 0; c < nchunks; ++c) s += part[c * ld + k];
             w = s * wfac[index ? static_cast<int64_t>(index[k]) : k];
             if (!isfinite(w)) atomicOr(flags, 1u);
+            if (wout) wout[k] = w;
         }
         tile_partial(w, threadIdx.x & 63, partials, k >> 6);
         return;
@@ -231,6 +234,96 @@ final_kernel(const double *__restrict__ partials, const int64_t *__restrict__ d_
     }
 }
 
+// ---------------------------------------------------------------- histograms
+
+// Largest photon pT, or smallest photon-pair Delta R (pseudorapidity and
+// azimuth as in the cuts; both invariant under the longitudinal boost).
+template <int N>
+__device__ __forceinline__ double observable_value(const double *__restrict__ mom, int64_t ld,
+                                                   int64_t col, int which)
+{
+    double pt[N], eta[N], phi[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const double x = mom[(9 + 4 * j) * ld + col], y = mom[(10 + 4 * j) * ld + col],
+                     z = mom[(11 + 4 * j) * ld + col];
+        const double pt2 = x * x + y * y;
+        pt[j] = sqrt(pt2);
+        eta[j] = copysign(fm::log((sqrt(pt2 + z * z) + fabs(z)) / pt[j]), z);
+        phi[j] = fm::atan2(y, x);
+    }
+    if (which == 0) {
+        double m = pt[0];
+#pragma unroll
+        for (int j = 1; j < N; ++j) m = fmax(m, pt[j]);
+        return m;
+    }
+    double m = INFINITY;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = i + 1; j < N; ++j) {
+            double dp = fabs(phi[i] - phi[j]);
+            dp = dp > M_PI ? 2.0 * M_PI - dp : dp;
+            const double de = eta[i] - eta[j];
+            m = fmin(m, sqrt(de * de + dp * dp));
+        }
+    return m;
+}
+
+// Fixed-point exponent: every weight and every partial sum stays below 2^62.
+__device__ __forceinline__ int hist_shift(const double *res)
+{
+    int e = 0;
+    frexp(res[0], &e);  // sum of weights < 2^e
+    return 62 - e;
+}
+
+template <int N>
+__global__ void __launch_bounds__(256)
+hist_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict__ index,
+            const double *__restrict__ w, const int64_t *__restrict__ d_count,
+            const double *__restrict__ res, int which, int nbins, double lo, double hi,
+            unsigned long long *__restrict__ bins)
+{
+    __shared__ unsigned long long lb[kHistMaxBins + 2];
+    for (int b = threadIdx.x; b < nbins + 2; b += 256) lb[b] = 0ull;
+    __syncthreads();
+    const int64_t count = *d_count;
+    const int shift = hist_shift(res);
+    const double scale = static_cast<double>(nbins) / (hi - lo);
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; k < count;
+         k += static_cast<int64_t>(gridDim.x) * 256) {
+        const double wk = w[k];
+        if (!(wk > 0.0) || !isfinite(wk)) continue;
+        const double x = observable_value<N>(mom, ld, index[k], which);
+        int b;
+        if (x < lo) {
+            b = 0;
+        } else if (!(x < hi)) {
+            b = nbins + 1;
+        } else {
+            b = 1 + static_cast<int>((x - lo) * scale);
+            b = b > nbins ? nbins : b;
+        }
+        atomicAdd(&lb[b], static_cast<unsigned long long>(llrint(ldexp(wk, shift))));
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins + 2; b += 256)
+        if (lb[b]) atomicAdd(&bins[b], lb[b]);
+}
+
+__global__ void hist_finish_kernel(const unsigned long long *__restrict__ bins, int nbins,
+                                   const double *__restrict__ res, int64_t n_gen,
+                                   double *__restrict__ hist)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbins + 2) return;
+    const int shift = hist_shift(res);
+    hist[b] = n_gen > 0 ? ldexp(static_cast<double>(bins[b]), -shift) / static_cast<double>(n_gen)
+                        : 0.0;
+}
+
 __global__ void zero_u32_kernel(unsigned *p, int count)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -284,12 +377,12 @@ hipError_t launch_compact(const uint8_t *flag, int64_t np, const int32_t *offset
 
 hipError_t launch_sum_chunks(const double *part, int nchunks, int64_t ld, const int64_t *d_count,
                              int64_t count, double *out, const int32_t *index, const double *wfac,
-                             double *partials, unsigned *flags, hipStream_t stream)
+                             double *partials, double *wout, unsigned *flags, hipStream_t stream)
 {
     const int64_t blocks = (count + 255) / 256;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(sum_chunks_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
-                       part, nchunks, ld, d_count, count, out, index, wfac, partials, flags);
+                       part, nchunks, ld, d_count, count, out, index, wfac, partials, wout, flags);
     return hipGetLastError();
 }
 
@@ -298,6 +391,44 @@ hipError_t launch_final(const double *partials, const int64_t *d_count, int64_t 
 {
     hipLaunchKernelGGL(final_kernel, dim3(1), dim3(kFinalThreads), 0, stream, partials, d_count,
                        n_gen, res, record);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t hist_n(const double *mom, int64_t ld, const int32_t *index, const double *w,
+                        const int64_t *d_count, int64_t max_count, const double *res, int which,
+                        int nbins, double lo, double hi, unsigned long long *bins,
+                        hipStream_t stream)
+{
+    int64_t blocks = (max_count + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
+    hipLaunchKernelGGL(hist_kernel<N>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                       mom, ld, index, w, d_count, res, which, nbins, lo, hi, bins);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist(int n, const double *mom, int64_t ld, const int32_t *index, const double *w,
+                       const int64_t *d_count, int64_t max_count, const double *res,
+                       int observable, int nbins, double lo, double hi, unsigned long long *bins,
+                       hipStream_t stream)
+{
+    switch (n) {
+    case 2: return hist_n<2>(mom, ld, index, w, d_count, max_count, res, observable, nbins, lo, hi, bins, stream);
+    case 3: return hist_n<3>(mom, ld, index, w, d_count, max_count, res, observable, nbins, lo, hi, bins, stream);
+    case 4: return hist_n<4>(mom, ld, index, w, d_count, max_count, res, observable, nbins, lo, hi, bins, stream);
+    case 5: return hist_n<5>(mom, ld, index, w, d_count, max_count, res, observable, nbins, lo, hi, bins, stream);
+    case 6: return hist_n<6>(mom, ld, index, w, d_count, max_count, res, observable, nbins, lo, hi, bins, stream);
+    case 7: return hist_n<7>(mom, ld, index, w, d_count, max_count, res, observable, nbins, lo, hi, bins, stream);
+    case 8: return hist_n<8>(mom, ld, index, w, d_count, max_count, res, observable, nbins, lo, hi, bins, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_hist_finish(const unsigned long long *bins, int nbins, const double *res,
+                              int64_t n_gen, double *hist, hipStream_t stream)
+{
+    hipLaunchKernelGGL(hist_finish_kernel, dim3((nbins + 2 + 255) / 256), dim3(256), 0, stream, bins,
+                       nbins, res, n_gen, hist);
     return hipGetLastError();
 }
 

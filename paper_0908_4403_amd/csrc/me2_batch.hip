@@ -42,8 +42,8 @@ __device__ __forceinline__ void batch_item(const SliceDesc &d, int64_t npts, int
 {
     // |M|^2 only: the weighted sums follow in a separate pass
     me2_item<R, N, BatchShape<R>::mb(N), BatchShape<R>::h, BatchShape<R>::cl, false>(
-        d.mom, d.ld, d.index, npts, tile, chunk, d.nchunks, d.coef, d.out, d.ld_out, d.wfac,
-        d.partials, flags, tab, lane);
+        d.mom, d.ld, d.index, nullptr, npts, tile, chunk, d.nchunks, d.coef, d.out, d.ld_out, d.wfac,
+        d.partials, nullptr, flags, tab, lane);
 }
 
 template <typename R>

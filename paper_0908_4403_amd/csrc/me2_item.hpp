@@ -16,17 +16,20 @@ namespace heget {
 // One work item: 64 points (one per lane) x one chunk of helicity walks.
 // `tab` is this wave's LDS photon table (kPhotonFields * N * 64 values of R).
 // Point i of the item is column index[i] of mom (column i without an index).
+// H = 0 selects helicity sampling: one walk per lane with the configuration
+// hel[column] (bit j set = photon j has helicity +1) instead of the sum.
 // Output: with kWeighted, `partials` set and one chunk, the tile's (sum,
 // compensation, sum of squares) of |M|^2 * wfac[column] (the Monte-Carlo
-// weights of eq. (1)-(2)); otherwise |M|^2 of the chunk at
-// out[chunk * ld_out + i].
+// weights of eq. (1)-(2)), and the weight itself at wout[i] when wout is set;
+// otherwise |M|^2 of the chunk at out[chunk * ld_out + i].
 template <typename R, int N, int MB, int H, int CL, bool kWeighted = true>
 __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t ld,
-                                         const int32_t *__restrict__ index, int64_t npts,
+                                         const int32_t *__restrict__ index,
+                                         const uint16_t *__restrict__ hel, int64_t npts,
                                          int64_t tile, int chunk, int nchunks, double coef,
                                          double *__restrict__ out, int64_t ld_out,
                                          const double *__restrict__ wfac,
-                                         double *__restrict__ partials,
+                                         double *__restrict__ partials, double *__restrict__ wout,
                                          unsigned *__restrict__ flags, R *tab, int lane)
 {
     constexpr bool kTopInLds = N > MB;
@@ -75,14 +78,20 @@ __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t
         }
     }
 
-    constexpr int kPasses = (1 << N) / H;
-    const int ppc = kPasses / nchunks;
-    const double s = tree_sum<R, N, MB, H, CL>(in, tab, lane, chunk * ppc, (chunk + 1) * ppc);
+    double s;
+    if constexpr (H == 0) {
+        s = tree_one<R, N, MB, CL>(in, tab, lane, static_cast<uint32_t>(hel[src]));
+    } else {
+        constexpr int kPasses = (1 << N) / H;
+        const int ppc = kPasses / nchunks;
+        s = tree_sum<R, N, MB, H, CL>(in, tab, lane, chunk * ppc, (chunk + 1) * ppc);
+    }
     double me2 = ldexp(coef * norm * s, 2 * m * (2 - N));
     if (!ok) me2 = __builtin_nan("");
     if (kWeighted && partials && nchunks == 1) {
         const double w = valid ? me2 * wfac[src] : 0.0;
         if (!isfinite(w)) atomicOr(flags, 1u);
+        if (wout && valid) wout[i] = w;
         tile_partial(w, lane, partials, tile);
     } else if (valid) {
         if (!isfinite(me2)) atomicOr(flags, 1u);
@@ -93,9 +102,9 @@ __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t
 template <typename R, int N, int MB, int H, int CL, int WPB>
 __global__ void __launch_bounds__(WPB * 64)
 me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict__ index,
-           const int64_t *__restrict__ d_count, int64_t count, int nchunks, double coef, double *__restrict__ out, int64_t ld_out,
+           const uint16_t *__restrict__ hel, const int64_t *__restrict__ d_count, int64_t count, int nchunks, double coef, double *__restrict__ out, int64_t ld_out,
            const double *__restrict__ wfac, double *__restrict__ partials,
-           unsigned *__restrict__ flags)
+           double *__restrict__ wout, unsigned *__restrict__ flags)
 {
     __shared__ R tab_all[N > MB ? WPB * kPhotonFields * N * 64 : 1];
     const int lane = threadIdx.x & 63;
@@ -107,8 +116,8 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
     const int64_t tile = item / nchunks;
     const int chunk = static_cast<int>(item - tile * nchunks);
     R *tab = tab_all + (N > MB ? wave * kPhotonFields * N * 64 : 0);
-    me2_item<R, N, MB, H, CL>(mom, ld, index, npts, tile, chunk, nchunks, coef, out, ld_out, wfac,
-                              partials, flags, tab, lane);
+    me2_item<R, N, MB, H, CL>(mom, ld, index, hel, npts, tile, chunk, nchunks, coef, out, ld_out, wfac,
+                              partials, wout, flags, tab, lane);
 }
 
 template <typename R, int N, int MB, int H, int CL, int WPB>

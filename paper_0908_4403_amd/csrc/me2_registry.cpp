@@ -12,6 +12,8 @@ extern const Me2Variant kShapesF32Lo[], kShapesF32Mid[], kShapesF32Hi[];
 extern const Me2Variant kShapesF64Lo[], kShapesF64Mid[], kShapesF64Hi[];
 extern const int kShapesF32LoCount, kShapesF32MidCount, kShapesF32HiCount;
 extern const int kShapesF64LoCount, kShapesF64MidCount, kShapesF64HiCount;
+extern const Me2Variant kShapesSampled[];
+extern const int kShapesSampledCount;
 
 static const std::vector<Me2Variant> &all_variants()
 {
@@ -41,6 +43,13 @@ const Me2Variant *me2_default(int prec, int n)
     return nullptr;
 }
 
+const Me2Variant *me2_sampled(int prec, int n)
+{
+    for (int i = 0; i < kShapesSampledCount; ++i)
+        if (kShapesSampled[i].prec == prec && kShapesSampled[i].n == n) return &kShapesSampled[i];
+    return nullptr;
+}
+
 hipError_t launch_me2(const Me2Variant &v, const Me2Args &a, hipStream_t stream)
 {
     const int64_t ntiles = (a.count + 63) / 64;
@@ -48,11 +57,12 @@ hipError_t launch_me2(const Me2Variant &v, const Me2Args &a, hipStream_t stream)
     if (items == 0) return hipSuccess;
     const int64_t blocks = (items + v.wpb - 1) / v.wpb;
     void *args[] = {const_cast<double **>(&a.mom), const_cast<int64_t *>(&a.ld),
-                    const_cast<int32_t **>(&a.index), const_cast<int64_t **>(&a.d_count), const_cast<int64_t *>(&a.count),
+                    const_cast<int32_t **>(&a.index), const_cast<uint16_t **>(&a.hel),
+                    const_cast<int64_t **>(&a.d_count), const_cast<int64_t *>(&a.count),
                     const_cast<int *>(&a.nchunks), const_cast<double *>(&a.coef),
                     const_cast<double **>(&a.out), const_cast<int64_t *>(&a.ld_out),
                     const_cast<double **>(&a.wfac), const_cast<double **>(&a.partials),
-                    const_cast<unsigned **>(&a.flags)};
+                    const_cast<double **>(&a.wout), const_cast<unsigned **>(&a.flags)};
     return hipLaunchKernel(v.func, dim3(static_cast<unsigned>(blocks)), dim3(v.wpb * 64), args, 0,
                            stream);
 }

@@ -401,4 +401,32 @@ __device__ __forceinline__ double tree_sum(const PointIn<R, N> &in, R *tab, int 
     return total;
 }
 
+// One walk per lane with the lane's own helicity configuration `cfg` (bit j
+// set = photon j has helicity +1): |ordering sum|^2 of that configuration
+// (scaled units, without the external normalisations).
+template <typename R, int N, int MB, int CL>
+__device__ __forceinline__ double tree_one(const PointIn<R, N> &in, R *tab, int lane, uint32_t cfg)
+{
+    Chain<R, 1> c0;
+    c0.g2r[0] = R(1);
+    c0.g2i[0] = R(0);
+    c0.g3r[0] = R(0);
+    c0.g3i[0] = R(0);
+    Acc<1> acc;
+    acc.re[0] = 0.0;
+    acc.im[0] = 0.0;
+    if constexpr (N <= MB) {
+        Slots<R, 1, N> S;
+#pragma unroll
+        for (int s = 0; s < N; ++s) {
+            S.k[s] = in.k[s];
+            S.v[s] = make_vert<R, 1>(in.k[s], cfg, s);
+        }
+        run_subtree<R, 1, N, CL>(S, in.p1, c0, in.q0, acc);
+    } else {
+        top_levels<R, N, MB, 1, CL, 0>(tab, lane, (1u << N) - 1u, cfg, in.p1, c0, in.q0, acc);
+    }
+    return acc.re[0] * acc.re[0] + acc.im[0] * acc.im[0];
+}
+
 }  // namespace heget

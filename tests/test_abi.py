@@ -57,12 +57,24 @@ def test_argument_checks_run_on_the_host():
             H.xsec(4, bad)
         assert e.value.status == H.ERR_RANGE
     for bad in (H.Config(sqrt_s=-1.0), H.Config(mode=7), H.Config(prec=3),
+                H.Config(helicity_sampling=2),
                 H.Config(mode=H.UNIFORM_SQRTSHAT, sqrt_shat_lo=500.0, sqrt_shat_hi=200.0),
                 H.Config(mode=H.PP_TOY, sqrt_s=100.0, sqrt_shat_lo=150.0),
                 H.Config(pt_min=float("nan")), H.Config(alpha=0.0)):
         with pytest.raises(H.HegetError) as e:
             H.xsec(4, bad)
         assert e.value.status == H.ERR_ARG, bad
+    with pytest.raises(H.HegetError) as e:
+        H.xsec_batch([3], [H.Config(helicity_sampling=1)])
+    assert e.value.status == H.ERR_ARG
+    for args, status in (((7, 10, 0.0, 1.0), H.ERR_ARG), ((H.OBS_PT_MAX, 0, 0.0, 1.0), H.ERR_RANGE),
+                         ((H.OBS_PT_MAX, 5000, 0.0, 1.0), H.ERR_RANGE),
+                         ((H.OBS_DR_MIN, 10, 1.0, 1.0), H.ERR_ARG)):
+        with pytest.raises(H.HegetError) as e:
+            H.xsec_hist(4, H.Config(), *args)
+        assert e.value.status == status, args
+    h, r = H.xsec_hist(4, H.Config(npoints=0), H.OBS_PT_MAX, 8, 0.0, 100.0)
+    assert r["n_gen"] == 0 and not h.any()
     with pytest.raises(H.HegetError):
         H.gen_points(3, float("inf"))
     with pytest.raises(H.HegetError):

@@ -146,3 +146,55 @@ def test_back_to_back_calls_match_one_by_one(H):
     host = buf.cpu().numpy()
     for k in range(len(cfgs)):
         assert H.result_from_bytes(host[k]) == ref[k], k
+
+
+@pytest.mark.parametrize("n,mode,extra,npoints", [
+    (2, "FIXED_SHAT", dict(sqrt_s=500.0, dr_min=0.0), 16384),
+    (3, "FIXED_SHAT", dict(sqrt_s=1000.0), 3000),
+    (4, "UNIFORM_SQRTSHAT", dict(sqrt_shat_lo=200.0, sqrt_shat_hi=2000.0), 2000),
+    (5, "PP_TOY", dict(sqrt_s=14000.0, sqrt_shat_lo=150.0), 1500),
+])
+def test_helicity_sampling_matches_oracle_same_sample(H, orc, n, mode, extra, npoints):
+    """One drawn helicity configuration per point (the paper's per-event
+    helicities): same draws, same |M_h|^2 estimator, same sigma as the oracle."""
+    kw = dict(seed=6, npoints=npoints, pt_min=20.0, eta_max=2.5, dr_min=0.4)
+    kw.update(extra)
+    for prec, tol in (("FP64", 1e-10), ("FP32", 1e-5)):
+        hc, oc = _cfgs(H, orc, getattr(H, mode), prec=getattr(H, prec), helicity_sampling=1, **kw)
+        got = H.xsec(n, hc)
+        want = orc.xsec(n, oc)
+        print(mode, n, prec, "sampled", got["sigma_fb"], want["sigma_fb"], got["n_acc"], flush=True)
+        assert got["n_acc"] == want["n_acc"]
+        assert abs(got["sigma_fb"] / want["sigma_fb"] - 1) < tol
+        assert abs(got["err_fb"] / want["err_fb"] - 1) < 1e-4
+
+
+def test_helicity_sampling_is_unbiased_on_the_device(H):
+    """n = 4, 2^18 points: the sampled sigma agrees with the summed sigma of the
+    same points within four combined standard errors."""
+    kw = dict(prec=H.FP32, seed=12, npoints=1 << 18, sqrt_s=1000.0)
+    s = H.xsec(4, H.Config(**kw))
+    h = H.xsec(4, H.Config(helicity_sampling=1, **kw))
+    assert h["n_acc"] == s["n_acc"]
+    assert abs(h["sigma_fb"] - s["sigma_fb"]) < 4.0 * (h["err_fb"] ** 2 + s["err_fb"] ** 2) ** 0.5
+
+
+@pytest.mark.parametrize("n,which,lo,hi,sampling", [
+    (4, "PT_MAX", 20.0, 500.0, 0), (4, "DR_MIN", 0.4, 4.0, 0), (3, "PT_MAX", 20.0, 500.0, 1),
+])
+def test_histogram_matches_oracle_same_sample(H, orc, n, which, lo, hi, sampling):
+    """Weighted distributions of Fig. 2's observables: per bin against the
+    oracle's histogram of the same points (FP64 path: 1e-10 relative per bin
+    with content; FP32: 1e-4 per bin, 1e-5 on the total), and the bins add up
+    to the call's sigma."""
+    kw = dict(seed=8, npoints=4000, sqrt_s=1000.0, pt_min=20.0, eta_max=2.5, dr_min=0.4)
+    oc = orc.Config(mode=0, helicity_sampling=sampling, **kw)
+    ref = orc.hist(n, oc, getattr(orc, which), 24, lo, hi)
+    for prec, tol_bin, tol_tot in (("FP64", 1e-10, 1e-10), ("FP32", 1e-4, 1e-5)):
+        hc = H.Config(mode=0, prec=getattr(H, prec), helicity_sampling=sampling, **kw)
+        got, r = H.xsec_hist(n, hc, getattr(H, "OBS_" + which), 24, lo, hi)
+        assert abs(got.sum() / r["sigma_fb"] - 1) < 1e-12
+        assert abs(got.sum() / ref.sum() - 1) < tol_tot
+        big = ref > 1e-3 * ref.max()
+        assert np.all(np.abs(got[big] / ref[big] - 1) < tol_bin), (prec, got, ref)
+        assert np.all((got > 0) == (ref > 0))

@@ -333,3 +333,87 @@ def test_pp_point_uses_both_beam_assignments(orc):
         if seen >= 5:
             break
     assert seen >= 5
+
+
+# ---- helicity sampling (the paper's per-event helicities, Section 3.1)
+
+def test_helicity_draw_is_a_nonvanishing_configuration_and_uniform(orc):
+    """Draws cover exactly the 2^(n+1) configurations with h_u != h_ubar, about
+    uniformly (chi-square over 2^(n+1) cells at n = 3, 20000 draws)."""
+    n = 3
+    counts = {}
+    for i in range(20000):
+        h1, h2, lam = orc.draw_helicity(n, 5, i)
+        assert h1 == -h2 and all(l in (-1, 1) for l in lam)
+        counts[(h1, lam)] = counts.get((h1, lam), 0) + 1
+    assert len(counts) == 2 ** (n + 1)
+    e = 20000 / 2 ** (n + 1)
+    chi2 = sum((c - e) ** 2 / e for c in counts.values())
+    assert chi2 < 40.0  # 15 degrees of freedom; p ~ 5e-4
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_sampled_estimator_averages_to_the_sum(orc, n):
+    """Averaged over every configuration a draw can give, 2^(n+1) |M_h|^2 is
+    the helicity sum (the estimator is unbiased), and the point's sampled
+    |M|^2 is that estimator for the drawn configuration."""
+    p = _events(orc, n, 1000.0, 41, 1)[0]
+    total = 0.0
+    for h1 in (-1, 1):
+        for lam in _lams(n):
+            total += 2 ** (n + 1) * abs(orc.amp(p, h1, -h1, lam)) ** 2
+    assert total / 2 ** (n + 1) == pytest.approx(orc.me2(p), rel=1e-13)
+    cfg = orc.Config(mode=0, seed=41, npoints=1, sqrt_s=1000.0, helicity_sampling=1,
+                     pt_min=0.0, eta_max=0.0, dr_min=0.0)
+    acc, ev, _, me, _ = orc.point(n, cfg, 0)
+    h1, h2, lam = orc.draw_helicity(n, 41, 0)
+    assert me == pytest.approx(2 ** (n + 1) * abs(orc.amp(ev, h1, h2, lam)) ** 2, rel=1e-14)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_rotation_keeps_each_helicity_amplitude(orc, n):
+    """The rotation by pi about x that swaps the quark directions leaves every
+    helicity amplitude's modulus unchanged (not only the sum), so one |M_h|^2
+    serves both beam assignments in sampling mode too."""
+    p = _events(orc, n, 900.0, 42, 1)[0]
+    r = p.copy()
+    r[:, 2] *= -1
+    r[:, 3] *= -1
+    for h1 in (-1, 1):
+        for lam in _lams(n):
+            a = abs(orc.amp(p, h1, -h1, lam)) ** 2
+            b = abs(orc.amp(r, h1, -h1, lam, u_along_minus_z=True)) ** 2
+            assert b == pytest.approx(a, rel=1e-12, abs=1e-30 * (a + b + 1e-300))
+
+
+def test_sampled_sigma_agrees_with_summed_sigma(orc):
+    """n = 2 at 500 GeV (config 1 cuts): the sampled sigma and the summed sigma
+    of the same points agree within their combined Monte-Carlo error."""
+    kw = dict(mode=0, seed=0, npoints=16384, sqrt_s=500.0, pt_min=20.0, eta_max=2.5, dr_min=0.0)
+    s = orc.xsec(2, orc.Config(**kw))
+    h = orc.xsec(2, orc.Config(helicity_sampling=1, **kw))
+    assert abs(h["sigma_fb"] - s["sigma_fb"]) < 4.0 * h["err_fb"]
+    assert h["n_acc"] == s["n_acc"] and h["err_fb"] > s["err_fb"]
+
+
+# ---- distributions (Fig. 2: leading photon pT, smallest photon-pair Delta R)
+
+def test_observables_on_hand_built_photons(orc):
+    import math
+    def photon(pt, eta, phi):
+        return [pt * math.cosh(eta), pt * math.cos(phi), pt * math.sin(phi), pt * math.sinh(eta)]
+    k = np.array([photon(30.0, 0.1, 3.0), photon(50.0, 0.1, -3.0), photon(40.0, 1.5, 0.5)])
+    assert orc.observable(k, orc.PT_MAX) == pytest.approx(50.0, rel=1e-14)
+    # photons 0 and 1: same eta, azimuths 3.0 and -3.0 are 2 pi - 6 apart across the wrap
+    assert orc.observable(k, orc.DR_MIN) == pytest.approx(2 * math.pi - 6.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("which,lo,hi", [(0, 20.0, 500.0), (1, 0.4, 4.0)])
+def test_histogram_entries_add_up_to_sigma(orc, which, lo, hi):
+    """Under- and overflow included, the bins hold every accepted weight once."""
+    cfg = orc.Config(mode=0, seed=3, npoints=3000, sqrt_s=1000.0)
+    h = orc.hist(3, cfg, which, 17, lo, hi)
+    s = orc.xsec(3, cfg)
+    assert h.sum() == pytest.approx(s["sigma_fb"], rel=1e-13)
+    assert h[0] == 0.0  # the cuts put every accepted point above lo
+    assert (h >= 0).all() and (h[1:-1] > 0).sum() >= 10
