@@ -78,6 +78,11 @@ def lib():
         L.orc_point.restype = C.c_int
         L.orc_xsec.argtypes = [C.c_int, C.POINTER(OrcConfig), C.POINTER(OrcResult), _dp]
         L.orc_draw_helicity.argtypes = [C.c_int, C.c_uint64, C.c_uint64, _ip, _ip, _ip]
+        L.orc_helas.argtypes = [C.c_int, _dp, _dp]
+        L.orc_me2_frame.argtypes = [C.c_int, _dp, C.c_double, C.c_double]
+        L.orc_me2_frame.restype = C.c_double
+        L.orc_me2_ffff.argtypes = [_dp, C.c_double, C.c_double, C.c_double]
+        L.orc_me2_ffff.restype = C.c_double
         L.orc_observable.argtypes = [C.c_int, _dp, C.c_int]
         L.orc_observable.restype = C.c_double
         L.orc_hist.argtypes = [C.c_int, C.POINTER(OrcConfig), C.c_int, C.c_int, C.c_double,
@@ -301,3 +306,28 @@ def hist(n: int, cfg: Config, which: int, nbins: int, lo: float, hi: float) -> n
     c = cfg.c()
     lib().orc_hist(n, C.byref(c), which, nbins, lo, hi, _ptr(out))
     return out
+
+
+HELAS_FUNCS = ["ixxxx0", "ixxxx1", "ixxxx2", "oxxxx0", "oxxxx1", "oxxxx2", "vxxxx0", "vxxxx1",
+               "vxxxx2", "iovxxx", "fvixx0", "fvoxx0", "jioxx0"]
+
+
+def helas(func: str, rec) -> np.ndarray:
+    """One record of the HELAS set (see orc_helas for the layouts)."""
+    x = _f64(np.asarray(rec, dtype=np.float64))
+    out = np.zeros(12)
+    k = lib().orc_helas(HELAS_FUNCS.index(func), _ptr(x), _ptr(out))
+    assert k > 0
+    return out[:k]
+
+
+def me2_frame(n: int, p, alpha: float = ALPHA, charge: float = CHARGE_U) -> float:
+    """Helicity-summed |M|^2 of u ubar -> n photons for momenta in any frame."""
+    x = _f64(np.asarray(p, dtype=np.float64).reshape(-1))
+    return lib().orc_me2_frame(n, _ptr(x), alpha, charge)
+
+
+def me2_ffff(p, alpha: float = ALPHA, q1: float = -1.0, q2: float = -1.0) -> float:
+    """Helicity-summed |M|^2 of f fbar -> f' fbar' through one photon."""
+    x = _f64(np.asarray(p, dtype=np.float64).reshape(-1))
+    return lib().orc_me2_ffff(_ptr(x), alpha, q1, q2)

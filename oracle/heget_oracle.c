@@ -364,6 +364,226 @@ static wf fvi(const wf *fi, const wf *vc, double gal0, double gal1)
     return r;
 }
 
+/* ---- the massless HELAS set in any direction (Appendix B.1-B.3) ----
+ * Written from the definitions: helicity eigenspinors of p with polar angles
+ * (theta, phi),
+ *   xi_+ = (cos(theta/2), e^{i phi} sin(theta/2)),
+ *   xi_- = (-e^{-i phi} sin(theta/2), cos(theta/2)),
+ * u(p, +1/2) = sqrt(2E) (0, 0, xi_+) and u(p, -1/2) = sqrt(2E) (xi_-, 0, 0) in
+ * the chiral representation (left-handed pair on top), v(p, h) = -u(p, -h),
+ * ubar = u^dagger gamma^0.  Polarisations eps(p, lam) = (-lam e_theta -
+ * i e_phi)/sqrt(2) and their conjugates (nsv = +1 for final-state vectors).
+ * Phase conventions on the z axis, where phi is undefined, are those of the
+ * HELAS functions: phi = 0 along +z; along -z phi = 0 for flowing-in spinors
+ * and phi = pi for flowing-out spinors and for vectors. */
+static void polar_angles(const double p[4], double *theta, double *phi, int minus_z_phi_pi)
+{
+    double pt = hypot(p[1], p[2]);
+    *theta = atan2(pt, p[3]);
+    if (pt > 0) *phi = atan2(p[2], p[1]);
+    else *phi = (p[3] < 0 && minus_z_phi_pi) ? M_PI : 0.0;
+}
+
+static wf spinor_in_any(const double p[4], int nhel, int nsf)
+{
+    wf w;
+    memset(&w, 0, sizeof w);
+    int h = nsf == 1 ? nhel : -nhel; /* v(p, h) = -u(p, -h) */
+    double th, ph;
+    polar_angles(p, &th, &ph, 0);
+    double r = sqrt(2.0 * p[0]) * (nsf == 1 ? 1.0 : -1.0);
+    if (h == 1) {
+        w.s[2] = r * cos(th / 2);
+        w.s[3] = r * cexp(_Complex_I * ph) * sin(th / 2);
+    } else {
+        w.s[0] = -r * cexp(-_Complex_I * ph) * sin(th / 2);
+        w.s[1] = r * cos(th / 2);
+    }
+    for (int m = 0; m < 4; ++m) w.p[m] = nsf * p[m];
+    return w;
+}
+
+static wf spinor_out_any(const double p[4], int nhel, int nsf)
+{
+    wf w;
+    memset(&w, 0, sizeof w);
+    int h = nsf == 1 ? nhel : -nhel;
+    double th, ph;
+    polar_angles(p, &th, &ph, 1);
+    double r = sqrt(2.0 * p[0]) * (nsf == 1 ? 1.0 : -1.0);
+    cplx c[4] = {0, 0, 0, 0};
+    if (h == 1) {
+        c[2] = r * cos(th / 2);
+        c[3] = r * cexp(_Complex_I * ph) * sin(th / 2);
+    } else {
+        c[0] = -r * cexp(-_Complex_I * ph) * sin(th / 2);
+        c[1] = r * cos(th / 2);
+    }
+    /* row u^dagger gamma^0: gamma^0 swaps the two pairs */
+    w.s[0] = conj(c[2]);
+    w.s[1] = conj(c[3]);
+    w.s[2] = conj(c[0]);
+    w.s[3] = conj(c[1]);
+    for (int m = 0; m < 4; ++m) w.p[m] = nsf * p[m];
+    return w;
+}
+
+static wf vector_any(const double k[4], int nhel, int nsv)
+{
+    wf w;
+    double th, ph;
+    polar_angles(k, &th, &ph, 1);
+    double eth[3] = {cos(th) * cos(ph), cos(th) * sin(ph), -sin(th)};
+    double eph[3] = {-sin(ph), cos(ph), 0.0};
+    w.s[0] = 0;
+    for (int m = 0; m < 3; ++m)
+        w.s[m + 1] = (-nhel * eth[m] + nsv * _Complex_I * eph[m]) / sqrt(2.0);
+    for (int m = 0; m < 4; ++m) w.p[m] = nsv * k[m];
+    return w;
+}
+
+/* off-shell vector current J^mu = d <fo| gamma^mu Gamma |fi>, q = p_fo - p_fi
+ * (jioxx0), Feynman gauge.  d = +1/q^2: with vertex factors i Gamma, fermion
+ * propagators i slash(q)/q^2 and photon propagators -i g/q^2, a tree amplitude
+ * is i M with M the product of Gamma's, -slash(q)/q^2 per fermion line and
+ * +g/q^2 per photon line, which fixes the signs of both d's. */
+static wf jio(const wf *fi, const wf *fo, double gal0, double gal1)
+{
+    wf r;
+    for (int m = 0; m < 4; ++m) r.p[m] = fo->p[m] - fi->p[m];
+    double d = 1.0 / mdot(r.p, r.p);
+    mat4 G = chiral_coupling(gal0, gal1);
+    cplx t[4];
+    mat_times(&G, fi->s, t);
+    for (int mu = 0; mu < 4; ++mu) {
+        cplx u[4];
+        row_times(fo->s, &GAMMA[mu], u);
+        cplx s = 0;
+        for (int i = 0; i < 4; ++i) s += u[i] * t[i];
+        r.s[mu] = d * s;
+    }
+    return r;
+}
+
+static void wf_unpack(const double *x, wf *w)
+{
+    for (int i = 0; i < 4; ++i) w->s[i] = x[2 * i] + _Complex_I * x[2 * i + 1];
+    for (int m = 0; m < 4; ++m) w->p[m] = x[8 + m];
+}
+
+static void wf_pack(const wf *w, double *x)
+{
+    for (int i = 0; i < 4; ++i) {
+        x[2 * i] = creal(w->s[i]);
+        x[2 * i + 1] = cimag(w->s[i]);
+    }
+    for (int m = 0; m < 4; ++m) x[8 + m] = w->p[m];
+}
+
+int orc_helas(int func, const double *in, double *out)
+{
+    init_gamma();
+    wf a, b, c, r;
+    switch (func) {
+    case 0: case 1: case 2: /* ixxxx0/1/2 */
+        r = spinor_in_any(in, (int)in[4], (int)in[5]);
+        wf_pack(&r, out);
+        return 12;
+    case 3: case 4: case 5: /* oxxxx0/1/2 */
+        r = spinor_out_any(in, (int)in[4], (int)in[5]);
+        wf_pack(&r, out);
+        return 12;
+    case 6: /* vxxxx0 */
+        r = vector_any(in, (int)in[4], (int)in[5]);
+        wf_pack(&r, out);
+        return 12;
+    case 7: case 8: /* vxxxx1/2: incoming vectors only, nsv is not read */
+        r = vector_any(in, (int)in[4], -1);
+        wf_pack(&r, out);
+        return 12;
+    case 9: { /* iovxxx(fi, fo, vc, gal) */
+        wf_unpack(in, &a);
+        wf_unpack(in + 12, &b);
+        wf_unpack(in + 24, &c);
+        cplx v = iov(&a, &b, &c, in[36], in[37]);
+        out[0] = creal(v);
+        out[1] = cimag(v);
+        return 2;
+    }
+    case 10: /* fvixx0(fi, vc, gal) */
+        wf_unpack(in, &a);
+        wf_unpack(in + 12, &c);
+        r = fvi(&a, &c, in[24], in[25]);
+        wf_pack(&r, out);
+        return 12;
+    case 11: /* fvoxx0(fo, vc, gal) */
+        wf_unpack(in, &b);
+        wf_unpack(in + 12, &c);
+        r = fvo(&b, &c, in[24], in[25]);
+        wf_pack(&r, out);
+        return 12;
+    case 12: /* jioxx0(fi, fo, gal) */
+        wf_unpack(in, &a);
+        wf_unpack(in + 12, &b);
+        r = jio(&a, &b, in[24], in[25]);
+        wf_pack(&r, out);
+        return 12;
+    default:
+        return -1;
+    }
+}
+
+/* forward declarations for the frame-independent evaluators below */
+static int next_perm(int *a, int n);
+
+/* Helicity-summed |M|^2 of u(p1) ubar(p2) -> n photons for momenta in any
+ * frame (eq. (6)-(8)), from the direction-general wavefunctions: u from
+ * ixxxx0, vbar from oxxxx0 (nSF = -1), eps* from vxxxx0 (nSV = +1), every
+ * ordering a chain of fvoxx0 closed with iovxxx.  All 2^(n+2) helicities. */
+double orc_me2_frame(int n, const double *p, double alpha, double charge)
+{
+    init_gamma();
+    double g = -sqrt(4.0 * M_PI * alpha) * charge;
+    double sum = 0.0;
+    for (int h1 = -1; h1 <= 1; h1 += 2)
+        for (int h2 = -1; h2 <= 1; h2 += 2)
+            for (int bits = 0; bits < (1 << n); ++bits) {
+                wf u = spinor_in_any(p, h1, 1), vb = spinor_out_any(p + 4, h2, -1), eps[8];
+                for (int i = 0; i < n; ++i)
+                    eps[i] = vector_any(p + 8 + 4 * i, ((bits >> i) & 1) ? 1 : -1, 1);
+                int a[8];
+                for (int i = 0; i < n; ++i) a[i] = i;
+                cplx total = 0;
+                do {
+                    wf w = vb;
+                    for (int j = 0; j < n - 1; ++j) w = fvo(&w, &eps[a[j]], g, g);
+                    total += iov(&u, &w, &eps[a[n - 1]], g, g);
+                } while (next_perm(a, n));
+                sum += creal(total) * creal(total) + cimag(total) * cimag(total);
+            }
+    return sum;
+}
+
+/* Helicity-summed |M|^2 of f(p1) fbar(p2) -> f'(p3) fbar'(p4) through one
+ * photon: the current jioxx0 of the incoming pair closed with iovxxx on the
+ * outgoing pair; couplings -e q1 and -e q2. */
+double orc_me2_ffff(const double *p, double alpha, double q1, double q2)
+{
+    init_gamma();
+    double e = sqrt(4.0 * M_PI * alpha);
+    double sum = 0.0;
+    for (int h = 0; h < 16; ++h) {
+        wf fi1 = spinor_in_any(p, (h & 1) ? 1 : -1, 1);
+        wf fo1 = spinor_out_any(p + 4, (h & 2) ? 1 : -1, -1);
+        wf fo2 = spinor_out_any(p + 8, (h & 4) ? 1 : -1, 1);
+        wf fi2 = spinor_in_any(p + 12, (h & 8) ? 1 : -1, -1);
+        wf j = jio(&fi1, &fo1, -e * q1, -e * q1);
+        cplx a = iov(&fi2, &fo2, &j, -e * q2, -e * q2);
+        sum += creal(a) * creal(a) + cimag(a) * cimag(a);
+    }
+    return sum;
+}
+
 /* next permutation in lexicographic order; returns 0 after the last one */
 static int next_perm(int *a, int n)
 {

@@ -148,6 +148,25 @@ double orc_observable(int n, const double *k, int observable);
 int orc_hist(int n, const orc_config *cfg, int observable, int nbins, double lo, double hi,
              double *hist);
 
+/* The massless HELAS set of Appendix B on one record, for the device
+ * library's tests.  func: 0-2 ixxxx0/1/2, 3-5 oxxxx0/1/2, 6-8 vxxxx0/1/2 (in
+ * = p[4], nhel, nsf or nsv; vxxxx1/2 give the incoming vector eps(p) with
+ * momentum -p whatever nsv says), 9 iovxxx (in = fi, fo, vc, gal0, gal1; out = re,
+ * im), 10 fvixx0 (fi, vc, gal0, gal1), 11 fvoxx0 (fo, vc, gal0, gal1),
+ * 12 jioxx0 (fi, fo, gal0, gal1).  A wavefunction is 12 doubles: four complex
+ * components (re, im) then the momentum along the flow.  Returns the number
+ * of doubles written, or -1 for an unknown func. */
+int orc_helas(int func, const double *in, double *out);
+
+/* Helicity-summed |M|^2 of u(p1) ubar(p2) -> n photons for momenta in any
+ * frame (p = p1, p2, k1..kn, (n+2)*4 doubles), built from ixxxx0, oxxxx0,
+ * vxxxx0, fvoxx0 and iovxxx; all 2^(n+2) helicities summed. */
+double orc_me2_frame(int n, const double *p, double alpha, double charge);
+
+/* Helicity-summed |M|^2 of f(p1) fbar(p2) -> f'(p3) fbar'(p4) through one
+ * photon (jioxx0 closed with iovxxx); charges q1, q2 in units of e. */
+double orc_me2_ffff(const double *p, double alpha, double q1, double q2);
+
 /* (hbar c)^2 in GeV^2 fb */
 double orc_gev2_fb(void);
 
