@@ -248,6 +248,60 @@ heget_status heget_kernel_shapes(int n, heget_prec prec, int max, heget_shape *s
  * restores the default.  HEGET_ERR_ARG if no such shape was compiled. */
 heget_status heget_set_kernel_shape(int n, heget_prec prec, const heget_shape *shape);
 
+/* ---- The massless HELAS set (Appendix B) as a device library ----
+ * Functions: B.1 external fermions (ixxxx0 any direction, ixxxx1 along +z,
+ * ixxxx2 along -z: flowing-in |fi>, u for nSF = +1 and v for nSF = -1;
+ * oxxxx0/1/2: flowing-out <fo|, ubar and vbar), B.2 massless vectors (vxxxx0
+ * any direction: eps* for nSV = +1, eps for nSV = -1; vxxxx1/2: incoming
+ * vectors along +z / -z, eps with momentum -p, nSV not read), B.3 the
+ * fermion-fermion-vector vertex of  psibar_F1 gamma^mu (gal0 P_L + gal1 P_R)
+ * psi_F2 V*_mu  (iovxxx: amplitude <fo|V|fi>; fvixx0: off-shell |f'> with
+ * p = p_fi - p_vc; fvoxx0: off-shell <f'| with p = p_fo + p_vc; jioxx0:
+ * off-shell vector current, Feynman gauge, p = p_fo - p_fi).  Massless
+ * fermion propagators carry -1/p^2, the vector propagator +1/p^2.
+ * The device header csrc/helas.hpp holds the same functions for use inside
+ * other HIP kernels; the entry points below evaluate one function on many
+ * independent records. */
+typedef enum {
+    HEGET_IXXXX0 = 0, HEGET_IXXXX1 = 1, HEGET_IXXXX2 = 2,
+    HEGET_OXXXX0 = 3, HEGET_OXXXX1 = 4, HEGET_OXXXX2 = 5,
+    HEGET_VXXXX0 = 6, HEGET_VXXXX1 = 7, HEGET_VXXXX2 = 8,
+    HEGET_IOVXXX = 9, HEGET_FVIXX0 = 10, HEGET_FVOXX0 = 11, HEGET_JIOXX0 = 12
+} heget_helas_fn;
+
+/* Record sizes of a function, in doubles.  A wavefunction is 12 doubles: the
+ * four complex components (re, im; spinors in the chiral basis with the
+ * left-handed pair first, vectors contravariant) then the momentum along the
+ * flow (p nSF or p nSV).  Inputs: external wavefunctions (p[4], nHEL, nSF or
+ * nSV) = 6; iovxxx (fi, fo, vc, gal0, gal1) = 38; fvixx0 (fi, vc, gal0,
+ * gal1), fvoxx0 (fo, vc, gal0, gal1), jioxx0 (fi, fo, gal0, gal1) = 26.
+ * Outputs: a wavefunction (12), or the vertex amplitude (re, im) = 2 for
+ * iovxxx.  HEGET_ERR_ARG for an unknown func or a null pointer. */
+heget_status heget_helas_sizes(int func, int *in_doubles, int *out_doubles);
+
+/* Evaluates `func` on count records: in[count][in_doubles] (host),
+ * out[count][out_doubles] (host); the arithmetic runs on the device in the
+ * precision `prec` (records are converted on the device).  nHEL, nSF and nSV
+ * must be +1 or -1.  Synchronous. */
+heget_status heget_helas(int func, int64_t count, const double *in, double *out, heget_prec prec);
+
+/* The same on device buffers d_in, d_out (same layouts), enqueued on stream. */
+heget_status heget_helas_device(int func, int64_t count, const double *d_in, double *d_out,
+                                heget_prec prec, heget_stream stream);
+
+/* Helicity-summed |M|^2 of u(p1) ubar(p2) -> n photons (2 <= n <= 5) for
+ * massless momenta in any frame, composed from the library functions
+ * (ixxxx0, oxxxx0, vxxxx0, fvoxx0 over all n! orderings, iovxxx).  Layouts
+ * as heget_me2 (momenta[npoints][n+2][4], host); the couplings of
+ * heget_set_couplings.  Every photon needs E > 0.  Equal to heget_me2 in the
+ * frame where it applies.  HEGET_ERR_RANGE for n outside 2..5. */
+heget_status heget_me2_frame(int n, int64_t npoints, const double *momenta, double *out_me2,
+                             heget_prec prec);
+
+/* Device-pointer form: d_mom[(n+2)*4][npoints] (SoA), d_out[npoints]. */
+heget_status heget_me2_frame_device(int n, int64_t npoints, const double *d_mom, double *d_out,
+                                    heget_prec prec, heget_stream stream);
+
 /* Vector-ALU ceiling of the current device: the FP32 and FP64 FMA rates (in
  * TFLOP/s, FMA = 2 flops) of a kernel of independent FMA chains with no
  * memory traffic, built like the amplitude kernels (no packed FP32).  Either

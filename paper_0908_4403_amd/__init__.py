@@ -44,6 +44,8 @@ EXPORTS = ["heget_gen_points", "heget_gen_points_device", "heget_me2", "heget_me
            "heget_timing_enable",
            "heget_timing_read", "heget_me2_flops", "heget_autotune", "heget_kernel_shapes",
            "heget_set_kernel_shape", "heget_valu_peak",
+           "heget_helas_sizes", "heget_helas", "heget_helas_device",
+           "heget_me2_frame", "heget_me2_frame_device",
            "heget_last_error", "heget_shutdown"]
 
 
@@ -115,6 +117,13 @@ def _load():
                                         C.POINTER(C.c_int)]
     lib.heget_set_kernel_shape.argtypes = [C.c_int, C.c_int, C.POINTER(Shape)]
     lib.heget_valu_peak.argtypes = [_dp, _dp]
+    lib.heget_helas_sizes.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.heget_helas.argtypes = [C.c_int, C.c_int64, _dp, _dp, C.c_int]
+    lib.heget_helas_device.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_int,
+                                       C.c_void_p]
+    lib.heget_me2_frame.argtypes = [C.c_int, C.c_int64, _dp, _dp, C.c_int]
+    lib.heget_me2_frame_device.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_int,
+                                           C.c_void_p]
     lib.heget_last_error.restype = C.c_char_p
     lib.heget_shutdown.restype = None
     for f in EXPORTS[:-2]:
@@ -395,3 +404,68 @@ def xsec_hist(n: int, cfg: Config, observable: int, nbins: int, lo: float, hi: f
     _check(_lib.heget_xsec_hist(n, C.byref(c), observable, nbins, lo, hi, _ptr(h), C.byref(r)),
            "heget_xsec_hist")
     return h, r.as_dict()
+
+
+# ---- the massless HELAS set (Appendix B) as a device library
+
+HELAS_FUNCS = ["ixxxx0", "ixxxx1", "ixxxx2", "oxxxx0", "oxxxx1", "oxxxx2", "vxxxx0", "vxxxx1",
+               "vxxxx2", "iovxxx", "fvixx0", "fvoxx0", "jioxx0"]
+
+
+def helas_sizes(func) -> tuple:
+    """(input doubles, output doubles) per record of a HELAS function."""
+    f = HELAS_FUNCS.index(func) if isinstance(func, str) else int(func)
+    ni, no = C.c_int(), C.c_int()
+    _check(_lib.heget_helas_sizes(f, C.byref(ni), C.byref(no)), "heget_helas_sizes")
+    return ni.value, no.value
+
+
+def helas(func, records, prec: int = FP64) -> np.ndarray:
+    """Evaluate one HELAS function on the device over records[count, in_doubles]."""
+    f = HELAS_FUNCS.index(func) if isinstance(func, str) else int(func)
+    ni, no = helas_sizes(f)
+    x = np.ascontiguousarray(records, dtype=np.float64)
+    if x.ndim != 2 or x.shape[1] != ni:
+        raise ValueError(f"records must have shape [count, {ni}]")
+    out = np.zeros((x.shape[0], no))
+    _check(_lib.heget_helas(f, x.shape[0], _ptr(x), _ptr(out), prec), "heget_helas")
+    return out
+
+
+def _device_f64(*ts) -> None:
+    for t in ts:
+        if str(t.dtype) != "torch.float64":
+            raise TypeError("device buffers must be float64")
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("device buffers must be contiguous GPU tensors")
+
+
+def helas_device(func, records, out, prec: int = FP64, stream=None) -> None:
+    """Device form of helas: records[count, in_doubles] and out[count, out_doubles] on the GPU."""
+    f = HELAS_FUNCS.index(func) if isinstance(func, str) else int(func)
+    ni, no = helas_sizes(f)
+    _device_f64(records, out)
+    if records.dim() != 2 or records.shape[1] != ni or tuple(out.shape) != (records.shape[0], no):
+        raise ValueError(f"shape mismatch: records[count, {ni}], out[count, {no}]")
+    _check(_lib.heget_helas_device(f, records.shape[0], records.data_ptr(), out.data_ptr(), prec,
+                                   _stream(stream)), "heget_helas_device")
+
+
+def me2_frame(momenta, prec: int = FP64, return_status: bool = False):
+    """Helicity-summed |M|^2 of u ubar -> n photons (n <= 5) at momenta[npoints, n+2, 4] in any frame."""
+    p = np.ascontiguousarray(momenta, dtype=np.float64)
+    if p.ndim != 3 or p.shape[2] != 4:
+        raise ValueError("momenta must have shape [npoints, n+2, 4]")
+    n = p.shape[1] - 2
+    out = np.zeros(p.shape[0])
+    st = _check(_lib.heget_me2_frame(n, p.shape[0], _ptr(p), _ptr(out), prec), "heget_me2_frame")
+    return (out, st) if return_status else out
+
+
+def me2_frame_device(n: int, mom_soa, out, prec: int = FP32, stream=None) -> None:
+    """Device form: mom_soa[(n+2)*4, npoints] and out[npoints], float64 on the GPU."""
+    _device_f64(mom_soa, out)
+    if mom_soa.shape[0] != (n + 2) * 4 or out.shape[0] != mom_soa.shape[1]:
+        raise ValueError("shape mismatch: mom_soa[(n+2)*4, npoints], out[npoints]")
+    _check(_lib.heget_me2_frame_device(n, out.shape[0], mom_soa.data_ptr(), out.data_ptr(), prec,
+                                       _stream(stream)), "heget_me2_frame_device")

@@ -1030,6 +1030,124 @@ heget_status heget_me2_device(int n, int64_t npoints, const double *d_mom, doubl
     return HEGET_OK;
 }
 
+heget_status heget_helas_sizes(int func, int *in_doubles, int *out_doubles)
+{
+    g_err.clear();
+    if (func < 0 || func >= heget::kHelasFuncs)
+        return fail(HEGET_ERR_ARG, "unknown HELAS function " + std::to_string(func));
+    if (!in_doubles || !out_doubles) return fail(HEGET_ERR_ARG, "null pointer");
+    *in_doubles = heget::helas_in_size(func);
+    *out_doubles = heget::helas_out_size(func);
+    return HEGET_OK;
+}
+
+heget_status heget_helas_device(int func, int64_t count, const double *d_in, double *d_out,
+                                heget_prec prec, heget_stream stream)
+{
+    g_err.clear();
+    if (func < 0 || func >= heget::kHelasFuncs)
+        return fail(HEGET_ERR_ARG, "unknown HELAS function " + std::to_string(func));
+    HG_TRY(check_np(count));
+    HG_TRY(check_prec(prec));
+    if (count > 0 && (!d_in || !d_out)) return fail(HEGET_ERR_ARG, "null pointer");
+    if (count == 0) return HEGET_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    HG_TRY(ensure_device());
+    HG_HIP(heget::launch_helas(func, prec, count, d_in, d_out, static_cast<hipStream_t>(stream)));
+    return HEGET_OK;
+}
+
+heget_status heget_helas(int func, int64_t count, const double *in, double *out, heget_prec prec)
+{
+    g_err.clear();
+    if (func < 0 || func >= heget::kHelasFuncs)
+        return fail(HEGET_ERR_ARG, "unknown HELAS function " + std::to_string(func));
+    HG_TRY(check_np(count));
+    HG_TRY(check_prec(prec));
+    if (count > 0 && (!in || !out)) return fail(HEGET_ERR_ARG, "null pointer");
+    if (count == 0) return HEGET_OK;
+    const size_t ni = size_t(heget::helas_in_size(func)), no = size_t(heget::helas_out_size(func));
+    if (func <= heget::kHelasVxxxx2)
+        for (int64_t i = 0; i < count; ++i) {
+            const double h = in[size_t(i) * ni + 4], f = in[size_t(i) * ni + 5];
+            if (!((h == 1.0 || h == -1.0) && (f == 1.0 || f == -1.0)))
+                return fail(HEGET_ERR_ARG, "record " + std::to_string(i) + ": nHEL and nSF/nSV must be +1 or -1");
+        }
+    std::lock_guard<std::mutex> lk(g_mu);
+    HG_TRY(ensure_device());
+    hipStream_t s = g.stream;
+    double *d_in, *d_out;
+    HG_TRY(scratch_bind(s));
+    HG_TRY(scratch_t<double>(S_MOM, ni * size_t(count), &d_in));
+    HG_TRY(scratch_t<double>(S_OUT, no * size_t(count), &d_out));
+    HG_HIP(hipMemcpyAsync(d_in, in, ni * size_t(count) * sizeof(double), hipMemcpyHostToDevice, s));
+    HG_HIP(heget::launch_helas(func, prec, count, d_in, d_out, s));
+    HG_HIP(hipMemcpyAsync(out, d_out, no * size_t(count) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HG_HIP(hipStreamSynchronize(s));
+    return HEGET_OK;
+}
+
+heget_status heget_me2_frame_device(int n, int64_t npoints, const double *d_mom, double *d_out,
+                                    heget_prec prec, heget_stream stream)
+{
+    g_err.clear();
+    if (n < 2 || n > heget::kFrameMaxN)
+        return fail(HEGET_ERR_RANGE, "n must be in 2.." + std::to_string(heget::kFrameMaxN) +
+                                         " for the frame evaluator, got " + std::to_string(n));
+    HG_TRY(check_np(npoints));
+    HG_TRY(check_prec(prec));
+    if (npoints > 0 && (!d_mom || !d_out)) return fail(HEGET_ERR_ARG, "null pointer");
+    if (npoints == 0) return HEGET_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    HG_TRY(ensure_device());
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned *d_flags;
+    HG_TRY(scratch_bind(s));
+    HG_TRY(scratch_t<unsigned>(S_FLAGS, 1, &d_flags));
+    const double coef = 0.5 * me2_coef(n, g_alpha, g_charge);  // (e Q)^(2n): both quark blocks are summed
+    HG_HIP(heget::launch_me2_frame(n, prec, npoints, d_mom, npoints, coef, d_out, d_flags, s));
+    return HEGET_OK;
+}
+
+heget_status heget_me2_frame(int n, int64_t npoints, const double *momenta, double *out_me2,
+                             heget_prec prec)
+{
+    g_err.clear();
+    if (n < 2 || n > heget::kFrameMaxN)
+        return fail(HEGET_ERR_RANGE, "n must be in 2.." + std::to_string(heget::kFrameMaxN) +
+                                         " for the frame evaluator, got " + std::to_string(n));
+    HG_TRY(check_np(npoints));
+    HG_TRY(check_prec(prec));
+    if (npoints > 0 && (!momenta || !out_me2)) return fail(HEGET_ERR_ARG, "null pointer");
+    if (npoints == 0) return HEGET_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    HG_TRY(ensure_device());
+    const size_t rows = size_t(n + 2) * 4;
+    std::vector<double> soa(rows * size_t(npoints));
+    for (int64_t i = 0; i < npoints; ++i)
+        for (size_t r = 0; r < rows; ++r) soa[r * size_t(npoints) + size_t(i)] = momenta[size_t(i) * rows + r];
+    double *d_mom, *d_out;
+    unsigned *d_flags;
+    hipStream_t s = g.stream;
+    HG_TRY(scratch_bind(s));
+    HG_TRY(scratch_t<double>(S_MOM, soa.size(), &d_mom));
+    HG_TRY(scratch_t<double>(S_OUT, size_t(npoints), &d_out));
+    HG_TRY(scratch_t<unsigned>(S_FLAGS, 1, &d_flags));
+    HG_HIP(hipMemcpyAsync(d_mom, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HG_HIP(heget::launch_zero_u32(d_flags, 1, s));
+    const double coef = 0.5 * me2_coef(n, g_alpha, g_charge);
+    HG_HIP(heget::launch_me2_frame(n, prec, npoints, d_mom, npoints, coef, d_out, d_flags, s));
+    unsigned flags = 0;
+    HG_HIP(hipMemcpyAsync(out_me2, d_out, size_t(npoints) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HG_HIP(hipMemcpyAsync(&flags, d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HG_HIP(hipStreamSynchronize(s));
+    if (flags & 1u) {
+        g_err = "some points gave a non-finite |M|^2 (check the preconditions)";
+        return HEGET_WARN_NONFINITE;
+    }
+    return HEGET_OK;
+}
+
 heget_status heget_xsec_async(int n, const heget_config *cfg, heget_result *out,
                               heget_stream stream)
 {

@@ -122,6 +122,28 @@ hipError_t launch_final(const double *partials, const int64_t *d_count, int64_t 
 hipError_t launch_fma_peak(int prec, void *out, int blocks, int iters, hipStream_t stream);
 double fma_peak_flops(int blocks, int iters);
 
+// HELAS device library over independent FP64 records (helas_kernels.hip).
+// func numbers the functions as heget_helas_fn does; a record holds
+// helas_in_size(func) doubles in and helas_out_size(func) doubles out.
+enum {
+    kHelasIxxxx0 = 0, kHelasIxxxx1, kHelasIxxxx2, kHelasOxxxx0, kHelasOxxxx1, kHelasOxxxx2,
+    kHelasVxxxx0, kHelasVxxxx1, kHelasVxxxx2, kHelasIovxxx, kHelasFvixx0, kHelasFvoxx0,
+    kHelasJioxx0, kHelasFuncs
+};
+__host__ __device__ constexpr int helas_in_size(int func)
+{
+    return func <= kHelasVxxxx2 ? 6 : func == kHelasIovxxx ? 38 : 26;
+}
+__host__ __device__ constexpr int helas_out_size(int func) { return func == kHelasIovxxx ? 2 : 12; }
+hipError_t launch_helas(int func, int prec, int64_t count, const double *in, double *out,
+                        hipStream_t stream);
+// |M|^2 of u ubar -> n photons (2 <= n <= kFrameMaxN) for momenta in any
+// frame, SoA [(n+2)*4][ld]; coef = (e Q)^(2n); bit 0 of *flags set if a
+// result is not finite.
+constexpr int kFrameMaxN = 5;
+hipError_t launch_me2_frame(int n, int prec, int64_t np, const double *mom, int64_t ld, double coef,
+                            double *out, unsigned *flags, hipStream_t stream);
+
 // Zero a small device buffer with a kernel (usable under stream capture).
 hipError_t launch_zero_u32(unsigned *p, int count, hipStream_t stream);
 

@@ -88,6 +88,32 @@ def test_empty_calls_need_no_device():
     import paper_0908_4403_amd as H
     assert H.me2(np.zeros((0, 6, 4))).shape == (0,)
     assert H.xsec(4, H.Config(npoints=0))["n_gen"] == 0
+    assert H.helas("fvoxx0", np.zeros((0, 26))).shape == (0, 12)
+    assert H.me2_frame(np.zeros((0, 7, 4))).shape == (0,)
+
+
+def test_helas_record_sizes_and_host_checks():
+    import paper_0908_4403_amd as H
+    sizes = [H.helas_sizes(f) for f in H.HELAS_FUNCS]
+    assert sizes == [(6, 12)] * 9 + [(38, 2), (26, 12), (26, 12), (26, 12)]
+    with pytest.raises(H.HegetError) as e:
+        H.helas_sizes(13)
+    assert e.value.status == H.ERR_ARG
+    with pytest.raises(ValueError):
+        H.helas("ixxxx0", np.zeros((3, 5)))
+    bad = np.array([[10.0, 0, 0, 10.0, 2.0, 1.0]])  # nHEL = 2
+    with pytest.raises(H.HegetError) as e:
+        H.helas("ixxxx0", bad)
+    assert e.value.status == H.ERR_ARG
+    bad[0, 4], bad[0, 5] = 1.0, 0.0                  # nSF = 0
+    with pytest.raises(H.HegetError):
+        H.helas("ixxxx0", bad)
+    with pytest.raises(H.HegetError) as e:
+        H.me2_frame(np.zeros((2, 8, 4)))             # n = 6: beyond the frame evaluator
+    assert e.value.status == H.ERR_RANGE
+    with pytest.raises(H.HegetError) as e:
+        H.me2_frame(np.zeros((2, 3, 4)))             # n = 1
+    assert e.value.status == H.ERR_RANGE
 
 
 def _flops_unshared(n, mb, h, cl):
