@@ -244,7 +244,7 @@ def main():
     peak = H.valu_peak()
     print(f"bench: measured FMA ceiling FP32 {peak['fp32_tflops']:.1f}, FP64 {peak['fp64_tflops']:.1f} TFLOP/s",
           file=sys.stderr, flush=True)
-    kname = f"me2_kernel<float,{n},{shape32[0]},{shape32[1]},{shape32[2]},{shape32[3]}>"
+    kname = "me2_kernel<float,{},{}>".format(n, ",".join(str(v) for v in shape32))
     from paper_0908_4403_amd.profiling import read_traffic
     traffic_md = os.path.join(ROOT, "profiles", f"me2_kernel_{args.workload}_hbm_traffic.md")
     traffic = read_traffic(traffic_md, kname)

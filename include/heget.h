@@ -214,9 +214,14 @@ heget_status heget_timing_read(double *me2_ms, int64_t *me2_launches, int reset)
  *                        the leaves); 2: the last two photons close together
  *                        through pair vectors built from the u end (the current
  *                        reuse of the paper's MadGraph program, Appendix A.1)
- *   waves_per_block      64-lane waves per workgroup */
+ *   waves_per_block      64-lane waves per workgroup
+ *   prefetch             0: one wave per 64-point work item; 1: only as many
+ *                        waves as the device holds at once, each looping over
+ *                        its items and loading the next item's inputs before
+ *                        the walk of the current one (hides the memory latency
+ *                        when few waves fit per SIMD, and shortens the tail) */
 typedef struct {
-    int32_t unrolled, helicities_per_walk, closing, waves_per_block;
+    int32_t unrolled, helicities_per_walk, closing, waves_per_block, prefetch;
 } heget_shape;
 
 /* Algorithmic floating-point operations per point of the amplitude kernel

@@ -62,10 +62,11 @@ class _Config(C.Structure):
 
 class Shape(C.Structure):
     _fields_ = [("unrolled", C.c_int32), ("helicities_per_walk", C.c_int32),
-                ("closing", C.c_int32), ("waves_per_block", C.c_int32)]
+                ("closing", C.c_int32), ("waves_per_block", C.c_int32), ("prefetch", C.c_int32)]
 
     def as_tuple(self):
-        return (self.unrolled, self.helicities_per_walk, self.closing, self.waves_per_block)
+        return (self.unrolled, self.helicities_per_walk, self.closing, self.waves_per_block,
+                self.prefetch)
 
 
 class Result(C.Structure):
@@ -342,7 +343,7 @@ def timing_read(reset: bool = True):
     return ms.value, cnt.value
 
 
-SHAPE_FIELDS = ("unrolled", "helicities_per_walk", "closing", "waves_per_block")
+SHAPE_FIELDS = ("unrolled", "helicities_per_walk", "closing", "waves_per_block", "prefetch")
 
 
 def me2_flops(n: int, prec: int = FP32):
@@ -363,7 +364,7 @@ def autotune(n: int, prec: int = FP32, npoints: int = 1 << 18) -> dict:
 
 def kernel_shapes(n: int, prec: int = FP32):
     """Compiled shapes for (n, prec) as tuples (unrolled, helicities_per_walk,
-    closing, waves_per_block), the shape in use first."""
+    closing, waves_per_block, prefetch), the shape in use first."""
     cnt = C.c_int()
     _check(_lib.heget_kernel_shapes(n, prec, 0, None, C.byref(cnt)), "heget_kernel_shapes")
     arr = (Shape * cnt.value)()

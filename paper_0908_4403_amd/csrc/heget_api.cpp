@@ -292,24 +292,25 @@ const heget::Me2Variant *pick_variant(int prec, int n)
     return heget::me2_default(prec, n);
 }
 
-const heget::Me2Variant *find_variant(int prec, int n, int mb, int h, int cl, int wpb)
+const heget::Me2Variant *find_variant(int prec, int n, int mb, int h, int cl, int wpb, int pf)
 {
     int cnt = 0;
     const heget::Me2Variant *v = heget::me2_variants(&cnt);
     for (int i = 0; i < cnt; ++i)
         if (v[i].prec == prec && v[i].n == n && v[i].mb == mb && v[i].h == h && v[i].cl == cl &&
-            v[i].wpb == wpb)
+            v[i].wpb == wpb && v[i].pf == pf)
             return &v[i];
     return nullptr;
 }
 
 heget_shape shape_of(const heget::Me2Variant &v)
 {
-    return heget_shape{v.mb, v.h, v.cl, v.wpb};
+    return heget_shape{v.mb, v.h, v.cl, v.wpb, v.pf};
 }
 
 // Tuning cache: one JSON object per line,
-// {"arch": "gfx950", "prec": 1, "n": 4, "mb": 4, "h": 2, "wpb": 4, "ms": 0.48, "points": 1048576}
+// {"arch": "gfx950", "prec": 1, "n": 4, "mb": 4, "h": 2, "cl": 2, "wpb": 4, "pf": 0, "ms": 0.48,
+//  "points": 1048576}
 void load_tuning_cache()
 {
     const char *path = std::getenv("HEGET_TUNING_CACHE");
@@ -319,11 +320,11 @@ void load_tuning_cache()
     char line[512];
     while (std::fgets(line, sizeof line, f)) {
         char arch[64] = {0};
-        int prec, n, mb, h, cl, wpb;
-        if (std::sscanf(line, " {\"arch\": \"%63[^\"]\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d",
-                        arch, &prec, &n, &mb, &h, &cl, &wpb) == 7 &&
+        int prec, n, mb, h, cl, wpb, pf;
+        if (std::sscanf(line, " {\"arch\": \"%63[^\"]\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d",
+                        arch, &prec, &n, &mb, &h, &cl, &wpb, &pf) == 8 &&
             g_arch == arch && prec >= 0 && prec < 2 && n >= 2 && n <= 8) {
-            const heget::Me2Variant *v = find_variant(prec, n, mb, h, cl, wpb);
+            const heget::Me2Variant *v = find_variant(prec, n, mb, h, cl, wpb, pf);
             if (v) g_tuned[prec][n] = v;
         }
     }
@@ -346,8 +347,8 @@ void save_tuning_cache(const heget::Me2Variant &v, double ms, int64_t points)
     }
     if (FILE *f = std::fopen(path, "w")) {
         for (const std::string &l : keep) std::fputs(l.c_str(), f);
-        std::fprintf(f, "{\"arch\": \"%s\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"ms\": %.6f, \"points\": %lld}\n",
-                     g_arch.c_str(), v.prec, v.n, v.mb, v.h, v.cl, v.wpb, ms, static_cast<long long>(points));
+        std::fprintf(f, "{\"arch\": \"%s\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d, \"ms\": %.6f, \"points\": %lld}\n",
+                     g_arch.c_str(), v.prec, v.n, v.mb, v.h, v.cl, v.wpb, v.pf, ms, static_cast<long long>(points));
         std::fclose(f);
     }
 }
@@ -1394,7 +1395,7 @@ heget_status heget_set_kernel_shape(int n, heget_prec prec, const heget_shape *s
     }
     const heget::Me2Variant *v =
         find_variant(prec, n, shape->unrolled, shape->helicities_per_walk, shape->closing,
-                     shape->waves_per_block);
+                     shape->waves_per_block, shape->prefetch);
     if (!v) return fail(HEGET_ERR_ARG, "no compiled kernel shape with these parameters");
     g_tuned[prec][n] = v;
     return HEGET_OK;

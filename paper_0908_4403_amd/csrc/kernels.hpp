@@ -16,6 +16,7 @@ struct Me2Variant {
     int h;      // helicity configurations per tree walk
     int cl;     // closing depth: 1 = photon by photon, 2 = last pair by pair vectors
     int wpb;    // waves per block
+    int pf;     // 1: resident waves loop over the items, loading the next one ahead
     const void *func;  // kernel symbol
 };
 

@@ -13,36 +13,66 @@
 
 namespace heget {
 
-// One work item: 64 points (one per lane) x one chunk of helicity walks.
-// `tab` is this wave's LDS photon table (kPhotonFields * N * 64 values of R).
-// Point i of the item is column index[i] of mom (column i without an index).
-// H = 0 selects helicity sampling: one walk per lane with the configuration
-// hel[column] (bit j set = photon j has helicity +1) instead of the sum.
+// The hardware estimate of 1/sqrt(x).  Used only for the vertex scale t,
+// whose rounding cancels exactly against the FP64 normalisation, so its
+// accuracy does not enter |M|^2.
+__device__ __forceinline__ float rsqrt_approx(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_approx(double x) { return __builtin_amdgcn_rsq(x); }
+
+// Inputs of one point of a work item, loaded ahead of the walk that uses them.
+template <int N>
+struct PointLoad {
+    double x[8 + 4 * N];  // momenta p1, p2, k1..kN
+    double wf;            // weight factor (0 without one)
+    uint32_t hel;         // sampled helicity configuration (0 without one)
+};
+
+// Column of mom holding lane `lane` of `tile`: past the last point the tile
+// repeats the last point (its result is not stored).
+__device__ __forceinline__ int64_t point_column(const int32_t *__restrict__ index, int64_t npts,
+                                                int64_t tile, int lane)
+{
+    const int64_t i = tile * 64 + lane;
+    const int64_t ic = i < npts ? i : npts - 1;
+    return index ? static_cast<int64_t>(index[ic]) : ic;
+}
+
+template <int N>
+__device__ __forceinline__ PointLoad<N> load_point(const double *__restrict__ mom, int64_t ld,
+                                                   int64_t src, const double *__restrict__ wfac,
+                                                   const uint16_t *__restrict__ hel)
+{
+    PointLoad<N> q;
+#pragma unroll
+    for (int r = 0; r < 8 + 4 * N; ++r) q.x[r] = mom[r * ld + src];
+    q.wf = wfac ? wfac[src] : 0.0;
+    q.hel = hel ? static_cast<uint32_t>(hel[src]) : 0u;
+    return q;
+}
+
+// The walk and epilogue of one work item: 64 points (one per lane) x one
+// chunk of helicity walks, from inputs already loaded.  `tab` is this wave's
+// LDS photon table (kPhotonFields * N * 64 values of R).  H = 0 selects
+// helicity sampling: one walk per lane with the configuration q.hel (bit j
+// set = photon j has helicity +1) instead of the sum.
 // Output: with kWeighted, `partials` set and one chunk, the tile's (sum,
-// compensation, sum of squares) of |M|^2 * wfac[column] (the Monte-Carlo
-// weights of eq. (1)-(2)), and the weight itself at wout[i] when wout is set;
-// otherwise |M|^2 of the chunk at out[chunk * ld_out + i].
+// compensation, sum of squares) of |M|^2 * wf (the Monte-Carlo weights of
+// eq. (1)-(2)), and the weight itself at wout[i] when wout is set; otherwise
+// |M|^2 of the chunk at out[chunk * ld_out + i].
 template <typename R, int N, int MB, int H, int CL, bool kWeighted = true>
-__device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t ld,
-                                         const int32_t *__restrict__ index,
-                                         const uint16_t *__restrict__ hel, int64_t npts,
-                                         int64_t tile, int chunk, int nchunks, double coef,
-                                         double *__restrict__ out, int64_t ld_out,
-                                         const double *__restrict__ wfac,
-                                         double *__restrict__ partials, double *__restrict__ wout,
-                                         unsigned *__restrict__ flags, R *tab, int lane)
+__device__ __forceinline__ void me2_compute(const PointLoad<N> &q, int64_t npts, int64_t tile,
+                                            int chunk, int nchunks, double coef,
+                                            double *__restrict__ out, int64_t ld_out,
+                                            double *__restrict__ partials, double *__restrict__ wout,
+                                            unsigned *__restrict__ flags, R *tab, int lane)
 {
     constexpr bool kTopInLds = N > MB;
     const int64_t i = tile * 64 + lane;
     const bool valid = i < npts;
-    const int64_t ic = valid ? i : npts - 1;  // ragged tail: repeat the last point
-    const int64_t src = index ? static_cast<int64_t>(index[ic]) : ic;
 
     // ---- FP64 set-up: preconditions, power-of-two scale, light-cone photons
-    const double E1 = mom[0 * ld + src], p1x = mom[1 * ld + src], p1y = mom[2 * ld + src],
-                 p1z = mom[3 * ld + src];
-    const double E2 = mom[4 * ld + src], p2x = mom[5 * ld + src], p2y = mom[6 * ld + src],
-                 p2z = mom[7 * ld + src];
+    const double E1 = q.x[0], p1x = q.x[1], p1y = q.x[2], p1z = q.x[3];
+    const double E2 = q.x[4], p2x = q.x[5], p2y = q.x[6], p2z = q.x[7];
     bool ok = p1x == 0.0 && p1y == 0.0 && p1z > 0.0 && p2x == 0.0 && p2y == 0.0 && p2z < 0.0;
     int m = 0;
     frexp(E1 + E2, &m);
@@ -53,21 +83,25 @@ __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t
     PointIn<R, N> in;
     in.q0 = {static_cast<R>(-(E2 + p2z) * sc), static_cast<R>(-(E2 - p2z) * sc), R(0), R(0), R(0)};
     in.p1 = {static_cast<R>((E1 + p1z) * sc), static_cast<R>((E1 - p1z) * sc), R(0), R(0), R(0)};
+    double norm_den = 1.0;  // product of the photons' 2 E^2 pT^2 t^2, divided out once
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         const int r = 8 + 4 * j;
-        const double E = mom[(r + 0) * ld + src] * sc, kx = mom[(r + 1) * ld + src] * sc,
-                     ky = mom[(r + 2) * ld + src] * sc, kz = mom[(r + 3) * ld + src] * sc;
+        const double E = q.x[r] * sc, kx = q.x[r + 1] * sc, ky = q.x[r + 2] * sc, kz = q.x[r + 3] * sc;
         const double pt2 = kx * kx + ky * ky;
         ok = ok && E > 0.0 && pt2 > 0.0;
-        // k+ k- = pT^2 for a massless photon; take the cancellation-free one directly
-        const double kp = kz >= 0.0 ? E + kz : pt2 / (E - kz);
-        const double km = kz >= 0.0 ? pt2 / (E + kz) : E - kz;
-        // vertex normalisation t ~ 1/(sqrt(2) E pT) in R; the exact remainder
-        // (1/(sqrt(2) E pT t))^2 goes into the FP64 normalisation
-        const R t = static_cast<R>(1.0 / sqrt(2.0 * E * E * pt2));
+        // k+ k- = pT^2 for a massless photon: the light-cone component free of
+        // cancellation is E + |kz|, the other one pT^2 / (E + |kz|)
+        const double big = E + fabs(kz);
+        const double small = pt2 / big;
+        const double kp = kz >= 0.0 ? big : small;
+        const double km = kz >= 0.0 ? small : big;
+        // vertex normalisation t ~ 1/(sqrt(2) E pT), any rounding of it: the
+        // remainder (1/(sqrt(2) E pT t))^2 goes into the FP64 normalisation
+        const double e2pt2 = 2.0 * E * E * pt2;
+        const R t = rsqrt_approx(static_cast<R>(e2pt2));
         const double td = static_cast<double>(t);
-        norm *= 1.0 / (2.0 * E * E * pt2 * td * td);
+        norm_den *= e2pt2 * td * td;
         in.k[j] = {static_cast<R>(kp), static_cast<R>(km), static_cast<R>(kx), static_cast<R>(ky), t};
         if constexpr (kTopInLds) {
             tab[0 * N * 64 + j * 64 + lane] = in.k[j].p;
@@ -80,16 +114,16 @@ __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t
 
     double s;
     if constexpr (H == 0) {
-        s = tree_one<R, N, MB, CL>(in, tab, lane, static_cast<uint32_t>(hel[src]));
+        s = tree_one<R, N, MB, CL>(in, tab, lane, q.hel);
     } else {
         constexpr int kPasses = (1 << N) / H;
         const int ppc = kPasses / nchunks;
         s = tree_sum<R, N, MB, H, CL>(in, tab, lane, chunk * ppc, (chunk + 1) * ppc);
     }
-    double me2 = ldexp(coef * norm * s, 2 * m * (2 - N));
+    double me2 = ldexp(coef * (norm / norm_den) * s, 2 * m * (2 - N));
     if (!ok) me2 = __builtin_nan("");
     if (kWeighted && partials && nchunks == 1) {
-        const double w = valid ? me2 * wfac[src] : 0.0;
+        const double w = valid ? me2 * q.wf : 0.0;
         if (!isfinite(w)) atomicOr(flags, 1u);
         if (wout && valid) wout[i] = w;
         tile_partial(w, lane, partials, tile);
@@ -99,10 +133,36 @@ __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t
     }
 }
 
-template <typename R, int N, int MB, int H, int CL, int WPB>
+// Load and compute one work item (used by the mixed-n batch kernel).
+template <typename R, int N, int MB, int H, int CL, bool kWeighted = true>
+__device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t ld,
+                                         const int32_t *__restrict__ index,
+                                         const uint16_t *__restrict__ hel, int64_t npts,
+                                         int64_t tile, int chunk, int nchunks, double coef,
+                                         double *__restrict__ out, int64_t ld_out,
+                                         const double *__restrict__ wfac,
+                                         double *__restrict__ partials, double *__restrict__ wout,
+                                         unsigned *__restrict__ flags, R *tab, int lane)
+{
+    const int64_t src = point_column(index, npts, tile, lane);
+    const double *wf = kWeighted && partials && nchunks == 1 ? wfac : nullptr;
+    const PointLoad<N> q = load_point<N>(mom, ld, src, wf, H == 0 ? hel : nullptr);
+    me2_compute<R, N, MB, H, CL, kWeighted>(q, npts, tile, chunk, nchunks, coef, out, ld_out,
+                                            partials, wout, flags, tab, lane);
+}
+
+// The amplitude kernel.  Work item k (64 points x one helicity chunk) goes to
+// wave k mod (number of waves); with PF = 0 the grid has one wave per item,
+// with PF = 1 it holds only the waves resident on the device and each wave
+// walks its items in turn, loading the next item's inputs (and the survivor
+// index of the one after) before the walk of the current one, so the walk
+// hides the memory latency even at one wave per SIMD.  The loop bounds are
+// the same on every lane of a wave.
+template <typename R, int N, int MB, int H, int CL, int WPB, int PF>
 __global__ void __launch_bounds__(WPB * 64)
 me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict__ index,
-           const uint16_t *__restrict__ hel, const int64_t *__restrict__ d_count, int64_t count, int nchunks, double coef, double *__restrict__ out, int64_t ld_out,
+           const uint16_t *__restrict__ hel, const int64_t *__restrict__ d_count, int64_t count,
+           int nchunks, double coef, double *__restrict__ out, int64_t ld_out,
            const double *__restrict__ wfac, double *__restrict__ partials,
            double *__restrict__ wout, unsigned *__restrict__ flags)
 {
@@ -110,21 +170,50 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int64_t npts = d_count ? *d_count : count;
-    const int64_t ntiles = (npts + 63) >> 6;
-    const int64_t item = static_cast<int64_t>(blockIdx.x) * WPB + wave;
-    if (item >= ntiles * nchunks) return;  // whole wave
-    const int64_t tile = item / nchunks;
-    const int chunk = static_cast<int>(item - tile * nchunks);
+    const int64_t nitems = ((npts + 63) >> 6) * nchunks;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * WPB;
+    int64_t item = static_cast<int64_t>(blockIdx.x) * WPB + wave;
+    if (item >= nitems) return;  // whole wave
     R *tab = tab_all + (N > MB ? wave * kPhotonFields * N * 64 : 0);
-    me2_item<R, N, MB, H, CL>(mom, ld, index, hel, npts, tile, chunk, nchunks, coef, out, ld_out, wfac,
-                              partials, wout, flags, tab, lane);
+    const double *wf = partials && nchunks == 1 ? wfac : nullptr;
+    const uint16_t *hl = H == 0 ? hel : nullptr;
+    if constexpr (PF == 0) {
+        for (; item < nitems; item += stride) {
+            const int64_t tile = item / nchunks;
+            const int chunk = static_cast<int>(item - tile * nchunks);
+            const PointLoad<N> q = load_point<N>(mom, ld, point_column(index, npts, tile, lane), wf, hl);
+            me2_compute<R, N, MB, H, CL>(q, npts, tile, chunk, nchunks, coef, out, ld_out, partials,
+                                         wout, flags, tab, lane);
+        }
+    } else {
+        PointLoad<N> cur = load_point<N>(mom, ld, point_column(index, npts, item / nchunks, lane), wf, hl);
+        int64_t next = item + stride;
+        int64_t src_next = next < nitems ? point_column(index, npts, next / nchunks, lane) : 0;
+        for (;;) {
+            PointLoad<N> nxt;
+            int64_t src_after = 0;
+            if (next < nitems) {
+                nxt = load_point<N>(mom, ld, src_next, wf, hl);
+                if (next + stride < nitems) src_after = point_column(index, npts, (next + stride) / nchunks, lane);
+            }
+            const int64_t tile = item / nchunks;
+            const int chunk = static_cast<int>(item - tile * nchunks);
+            me2_compute<R, N, MB, H, CL>(cur, npts, tile, chunk, nchunks, coef, out, ld_out, partials,
+                                         wout, flags, tab, lane);
+            if (next >= nitems) break;
+            item = next;
+            next += stride;
+            cur = nxt;
+            src_next = src_after;
+        }
+    }
 }
 
-template <typename R, int N, int MB, int H, int CL, int WPB>
+template <typename R, int N, int MB, int H, int CL, int WPB, int PF = 0>
 constexpr Me2Variant variant()
 {
-    return Me2Variant{std::is_same<R, float>::value ? 1 : 0, N, MB, H, CL, WPB,
-                      reinterpret_cast<const void *>(&me2_kernel<R, N, MB, H, CL, WPB>)};
+    return Me2Variant{std::is_same<R, float>::value ? 1 : 0, N, MB, H, CL, WPB, PF,
+                      reinterpret_cast<const void *>(&me2_kernel<R, N, MB, H, CL, WPB, PF>)};
 }
 
 }  // namespace heget

@@ -1,6 +1,8 @@
 // Registry of the compiled amplitude-kernel shapes and their launcher.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "kernels.hpp"
@@ -50,12 +52,35 @@ const Me2Variant *me2_sampled(int prec, int n)
     return nullptr;
 }
 
+// Blocks of a kernel that fit on the device at once (resident), per kernel.
+static int64_t resident_blocks(const Me2Variant &v)
+{
+    static std::mutex mu;
+    static std::map<const void *, int64_t> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(v.func);
+    if (it != cache.end()) return it->second;
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v.func, v.wpb * 64, 0) != hipSuccess ||
+        per_cu <= 0 || cus <= 0)
+        return 0;  // unknown: one wave per item
+    const int64_t r = static_cast<int64_t>(per_cu) * cus;
+    cache[v.func] = r;
+    return r;
+}
+
 hipError_t launch_me2(const Me2Variant &v, const Me2Args &a, hipStream_t stream)
 {
     const int64_t ntiles = (a.count + 63) / 64;
     const int64_t items = ntiles * a.nchunks;
     if (items == 0) return hipSuccess;
-    const int64_t blocks = (items + v.wpb - 1) / v.wpb;
+    int64_t blocks = (items + v.wpb - 1) / v.wpb;
+    if (v.pf) {
+        const int64_t r = resident_blocks(v);
+        if (r > 0 && r < blocks) blocks = r;
+    }
     void *args[] = {const_cast<double **>(&a.mom), const_cast<int64_t *>(&a.ld),
                     const_cast<int32_t **>(&a.index), const_cast<uint16_t **>(&a.hel),
                     const_cast<int64_t **>(&a.d_count), const_cast<int64_t *>(&a.count),

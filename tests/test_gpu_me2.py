@@ -144,7 +144,7 @@ def test_autotune_picks_a_compiled_shape(H, orc, tmp_path, monkeypatch):
     assert shape == H.kernel_shapes(5, H.FP32)[0]
     assert r["ms"] > 0
     line = cache.read_text().strip()
-    assert f'"n": 5, "mb": {shape[0]}, "h": {shape[1]}, "cl": {shape[2]}, "wpb": {shape[3]}' in line
+    assert f'"n": 5, "mb": {shape[0]}, "h": {shape[1]}, "cl": {shape[2]}, "wpb": {shape[3]}, "pf": {shape[4]}' in line
     ev = cut_events(orc, 5, 1000.0, 17, 100)
     ref, _ = orc.me2_batch(ev)
     assert np.median(np.abs(H.me2(ev, H.FP32) / ref - 1)) <= 1e-5
