@@ -213,7 +213,11 @@ heget_status heget_timing_read(double *me2_ms, int64_t *me2_launches, int reset)
  *   closing              1: every ordering closes photon by photon (iovxx0 at
  *                        the leaves); 2: the last two photons close together
  *                        through pair vectors built from the u end (the current
- *                        reuse of the paper's MadGraph program, Appendix A.1)
+ *                        reuse of the paper's MadGraph program, Appendix A.1);
+ *                        3: as 2, and the two photons before them are summed
+ *                        over both orders at the ubar end, where the two
+ *                        currents share their propagator, so four photons
+ *                        close with 6 pair products instead of 12
  *   waves_per_block      64-lane waves per workgroup
  *   prefetch             0: one wave per 64-point work item; 1: only as many
  *                        waves as the device holds at once, each looping over

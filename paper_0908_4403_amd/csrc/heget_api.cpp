@@ -411,14 +411,26 @@ struct Walk {
             // subtree entry: vertex blocks of its slots, pair vectors
             for (int s = 0; s < n; ++s)
                 if (left >> s & 1u) total += 3.0 + 4.0 * var_count(1u << s);
-            if (cl == 2) subtree_pairs(left);
+            if (cl >= 2) subtree_pairs(left);
         }
         if (cl == 1 && nleft == 1) {
             total += 12.0 * H;
             return;
         }
-        if (cl == 2 && nleft == 2) {
+        if (cl >= 2 && nleft == 2) {
             total += 16.0 * H;
+            return;
+        }
+        if (cl == 3 && nleft == 4 && nleft <= mb) {
+            // pair sums at both ends: four single-photon updates, then per
+            // split {x, y} | {a, b}: the propagator of q + k_x + k_y, two vertex
+            // halves and their sum, one propagator half and one pair closing
+            for (int s = 0; s < n; ++s)
+                if (left >> s & 1u) total += 14.0 + 40.0 * var_count(used | (1u << s));
+            for (int x = 0; x < n; ++x)
+                for (int y = x + 1; y < n; ++y)
+                    if ((left >> x & 1u) && (left >> y & 1u))
+                        total += 14.0 + 64.0 * var_count(used | (1u << x) | (1u << y)) + 16.0 * H;
             return;
         }
         for (int s = 0; s < n; ++s) {

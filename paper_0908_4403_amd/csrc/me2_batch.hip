@@ -7,15 +7,15 @@ namespace heget {
 
 // ---------------------------------------------------------------- mixed-n batch
 
-// Shapes inside the mixed kernel.  Its register allocation is the largest of
-// its branches, so every branch is kept within the budget of two waves per
-// SIMD in FP32: n = 8 takes the 3-level unroll there.
+// Shapes inside the mixed kernel: 4-level unrolled subtrees whose last four
+// photons close with pair sums at both ends.  Its register allocation is the
+// largest of its branches: one wave per SIMD in both precisions, no spills.
 template <typename R>
 struct BatchShape {
     static constexpr bool fp32 = std::is_same<R, float>::value;
-    static constexpr int mb(int n) { return n < 4 ? n : (fp32 ? (n == 8 ? 3 : 4) : 3); }
+    static constexpr int mb(int n) { return n < 4 ? n : 4; }
     static constexpr int h = fp32 ? 2 : 1;
-    static constexpr int cl = 2;
+    static constexpr int cl = 3;
 };
 
 __device__ __forceinline__ int64_t wave_broadcast(int64_t v)

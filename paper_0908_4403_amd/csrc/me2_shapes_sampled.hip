@@ -6,12 +6,12 @@
 namespace heget {
 
 extern const Me2Variant kShapesSampled[] = {
-    variant<float, 2, 2, 0, 2, 4>(), variant<float, 3, 3, 0, 2, 4>(), variant<float, 4, 4, 0, 2, 4>(),
-    variant<float, 5, 4, 0, 2, 4>(), variant<float, 6, 4, 0, 2, 4>(), variant<float, 7, 4, 0, 2, 4>(),
-    variant<float, 8, 4, 0, 2, 4>(),
-    variant<double, 2, 2, 0, 2, 4>(), variant<double, 3, 3, 0, 2, 4>(), variant<double, 4, 4, 0, 2, 4>(),
-    variant<double, 5, 4, 0, 2, 4>(), variant<double, 6, 4, 0, 2, 4>(), variant<double, 7, 4, 0, 2, 4>(),
-    variant<double, 8, 4, 0, 2, 4>(),
+    variant<float, 2, 2, 0, 2, 4>(), variant<float, 3, 3, 0, 2, 4>(), variant<float, 4, 4, 0, 3, 4>(),
+    variant<float, 5, 4, 0, 3, 4>(), variant<float, 6, 4, 0, 3, 4>(), variant<float, 7, 4, 0, 3, 4>(),
+    variant<float, 8, 4, 0, 3, 4>(),
+    variant<double, 2, 2, 0, 2, 4>(), variant<double, 3, 3, 0, 2, 4>(), variant<double, 4, 4, 0, 3, 4>(),
+    variant<double, 5, 4, 0, 3, 4>(), variant<double, 6, 4, 0, 3, 4>(), variant<double, 7, 4, 0, 3, 4>(),
+    variant<double, 8, 4, 0, 3, 4>(),
 };
 extern const int kShapesSampledCount = sizeof(kShapesSampled) / sizeof(Me2Variant);
 

@@ -164,22 +164,45 @@ __device__ __forceinline__ Prop<R> propagate(const LMom<R> &q, const LMom<R> &k,
     return {d * qn.m, d * qn.p, d * qn.x, d * qn.y};
 }
 
+// The vertex half of a current update, (sl1, sl2) = V' g, for every variant.
+template <typename R, int H>
+struct Half {
+    R s1r[H], s1i[H], s2r[H], s2i[H];
+};
+
+template <typename R, int H>
+__device__ __forceinline__ Half<R, H> vertex_half(const Vert<R, H> &v, const Chain<R, H> &c)
+{
+    Half<R, H> s;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        s.s1r[h] = v.a3[h] * c.g2r[h] + v.br[h] * c.g3r[h] - v.bi[h] * c.g3i[h];
+        s.s1i[h] = v.a3[h] * c.g2i[h] + v.br[h] * c.g3i[h] + v.bi[h] * c.g3r[h];
+        s.s2r[h] = v.gr[h] * c.g2r[h] - v.gi[h] * c.g2i[h] - v.a3[h] * c.g3r[h];
+        s.s2i[h] = v.gr[h] * c.g2i[h] + v.gi[h] * c.g2r[h] - v.a3[h] * c.g3i[h];
+    }
+    return s;
+}
+
+// The propagator half: g' = d P(q') (sl1, sl2).
+template <typename R, int H>
+__device__ __forceinline__ void propagator_half(const Prop<R> &P, const Half<R, H> &s, Chain<R, H> &o)
+{
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        o.g2r[h] = P.m * s.s1r[h] - P.x * s.s2r[h] + P.y * s.s2i[h];
+        o.g2i[h] = P.m * s.s1i[h] - P.x * s.s2i[h] - P.y * s.s2r[h];
+        o.g3r[h] = P.p * s.s2r[h] - P.x * s.s1r[h] - P.y * s.s1i[h];
+        o.g3i[h] = P.p * s.s2i[h] - P.x * s.s1i[h] + P.y * s.s1r[h];
+    }
+}
+
 // One fvoxx0 current update for every variant.
 template <typename R, int H>
 __device__ __forceinline__ void update(const Vert<R, H> &v, const Chain<R, H> &c, const Prop<R> &P,
                                        Chain<R, H> &o)
 {
-#pragma unroll
-    for (int h = 0; h < H; ++h) {
-        const R s1r = v.a3[h] * c.g2r[h] + v.br[h] * c.g3r[h] - v.bi[h] * c.g3i[h];
-        const R s1i = v.a3[h] * c.g2i[h] + v.br[h] * c.g3i[h] + v.bi[h] * c.g3r[h];
-        const R s2r = v.gr[h] * c.g2r[h] - v.gi[h] * c.g2i[h] - v.a3[h] * c.g3r[h];
-        const R s2i = v.gr[h] * c.g2i[h] + v.gi[h] * c.g2r[h] - v.a3[h] * c.g3i[h];
-        o.g2r[h] = P.m * s1r - P.x * s2r + P.y * s2i;
-        o.g2i[h] = P.m * s1i - P.x * s2i - P.y * s2r;
-        o.g3r[h] = P.p * s2r - P.x * s1r - P.y * s1i;
-        o.g3i[h] = P.p * s2i - P.x * s1i + P.y * s1r;
-    }
+    propagator_half<R, H>(P, vertex_half<R, H>(v, c), o);
 }
 
 // Closing vertex (iovxx0 with the u spinor): amp = gamma g2 - a3 g3, summed in FP64.
@@ -270,15 +293,66 @@ __device__ __forceinline__ void close_pair(const PairTab<R, H, NS> &T, int a, in
     }
 }
 
+// The last four photons of every ordering below a node (slots in MASK,
+// four of them) with pair sums at both ends (CL = 3).  The 24 orderings
+// (x, y, a, b) group by the split {x, y} | {a, b}: the u end contributes the
+// pair vector U_ab (both orders of a, b), the ubar end the sum of the
+// currents after x then y and after y then x.  Those two currents carry the
+// same momentum q + k_x + k_y, so they share their propagator:
+//     G_xy = d P(q + k_x + k_y) [V_y g_x + V_x g_y],  g_x = current after x,
+// and the node closes with six products U_ab . G_xy instead of twelve.
+template <typename R, int H, int NS, unsigned MASK, typename PT>
+__device__ __forceinline__ void quad_close(const Slots<R, H, NS> &S, const PT &T, const Chain<R, H> &c,
+                                           const LMom<R> &q, Acc<H> &acc)
+{
+    constexpr int s0 = __builtin_ctz(MASK);
+    constexpr unsigned m1 = MASK & (MASK - 1u);
+    constexpr int s1 = __builtin_ctz(m1);
+    constexpr unsigned m2 = m1 & (m1 - 1u);
+    constexpr int s2 = __builtin_ctz(m2);
+    constexpr int s3 = __builtin_ctz(m2 & (m2 - 1u));
+    constexpr int sl[4] = {s0, s1, s2, s3};
+    Chain<R, H> g1[4];
+    LMom<R> q1[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const Prop<R> P = propagate<R>(q, S.k[sl[i]], q1[i]);
+        update<R, H>(S.v[sl[i]], c, P, g1[i]);
+    }
+    // (x, y) index pairs into sl and the closing pair (a, b) of the other two
+    constexpr int X[6] = {0, 0, 0, 1, 1, 2}, Y[6] = {1, 2, 3, 2, 3, 3};
+    constexpr int A[6] = {2, 1, 1, 0, 0, 0}, B[6] = {3, 3, 2, 3, 2, 1};
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        LMom<R> q2;
+        const Prop<R> P = propagate<R>(q1[X[t]], S.k[sl[Y[t]]], q2);
+        Half<R, H> s = vertex_half<R, H>(S.v[sl[Y[t]]], g1[X[t]]);
+        const Half<R, H> s2 = vertex_half<R, H>(S.v[sl[X[t]]], g1[Y[t]]);
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            s.s1r[h] += s2.s1r[h];
+            s.s1i[h] += s2.s1i[h];
+            s.s2r[h] += s2.s2r[h];
+            s.s2i[h] += s2.s2i[h];
+        }
+        Chain<R, H> g2;
+        propagator_half<R, H>(P, s, g2);
+        close_pair<R, H, NS>(T, sl[A[t]], sl[B[t]], g2, acc);
+    }
+}
+
 // Unrolled subtree over the slot photons in MASK, entered with current c at
-// momentum q.  CL = 1 closes photon by photon; CL = 2 closes the last pair.
+// momentum q.  CL = 1 closes photon by photon; CL = 2 closes the last pair;
+// CL = 3 closes the last four photons with pair sums at both ends.
 template <typename R, int H, int NS, int CL, unsigned MASK, typename PT>
 __device__ __forceinline__ void subtree(const Slots<R, H, NS> &S, const PT &T, const Chain<R, H> &c,
                                         const LMom<R> &q, Acc<H> &acc)
 {
     if constexpr (CL == 1 && __builtin_popcount(MASK) == 1) {
         close_chain<R, H>(S.v[__builtin_ctz(MASK)], c, acc);
-    } else if constexpr (CL == 2 && __builtin_popcount(MASK) == 2) {
+    } else if constexpr (CL == 3 && __builtin_popcount(MASK) == 4) {
+        quad_close<R, H, NS, MASK>(S, T, c, q, acc);
+    } else if constexpr (CL >= 2 && __builtin_popcount(MASK) == 2) {
         constexpr int a = __builtin_ctz(MASK);
         constexpr int b = __builtin_ctz(MASK & (MASK - 1u));
         close_pair<R, H, NS>(T, a, b, c, acc);
@@ -294,12 +368,12 @@ __device__ __forceinline__ void subtree(const Slots<R, H, NS> &S, const PT &T, c
     }
 }
 
-// Enter a subtree over all NS slots (builds the pair vectors first for CL = 2).
+// Enter a subtree over all NS slots (builds the pair vectors first for CL >= 2).
 template <typename R, int H, int NS, int CL>
 __device__ __forceinline__ void run_subtree(const Slots<R, H, NS> &S, const LMom<R> &p1,
                                             const Chain<R, H> &c, const LMom<R> &q, Acc<H> &acc)
 {
-    if constexpr (CL == 2) {
+    if constexpr (CL >= 2) {
         PairTab<R, H, NS> T;
         make_pairs<R, H, NS>(S, p1, T);
         subtree<R, H, NS, CL, (1u << NS) - 1u>(S, T, c, q, acc);

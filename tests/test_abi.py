@@ -122,11 +122,22 @@ def _flops_unshared(n, mb, h, cl):
     import math
     f = math.factorial
     ns = min(n, mb)
+    if cl == 3 and ns < 4:  # no four-photon subtree: closes as pairs
+        cl = 2
     nodes = sum(f(n) // f(n - j) for j in range(1, n - cl + 1))
     subtrees = f(n) // f(ns)
     top = sum(f(n) // f(n - j) for j in range(1, n - ns + 1))
     walk = nodes * (14 + 40 * h) + (ns * subtrees + top) * (3 + 4 * h) + 4 * h
-    if cl == 1:
+    if cl == 3 and ns >= 4:
+        # the last four photons of every ordering: n!/4! nodes, each with four
+        # single-photon updates and six splits (propagator, two vertex halves
+        # and their sum, propagator half, pair closing)
+        quads = f(n) // f(4)
+        nodes = sum(f(n) // f(n - j) for j in range(1, n - 4 + 1))
+        walk = nodes * (14 + 40 * h) + (ns * subtrees + top) * (3 + 4 * h) + 4 * h
+        walk += quads * (4 * (14 + 40 * h) + 6 * (14 + 64 * h + 16 * h))
+        walk += subtrees * (ns * (12 + 14 * h) + ns * (ns - 1) * 20 * h + ns * (ns - 1) // 2 * 4 * h)
+    elif cl == 1:
         walk += f(n) * 12 * h
     else:
         walk += f(n) // 2 * 16 * h
