@@ -62,10 +62,10 @@ __device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t poi
 
 // 1 if every photon has pT > pt_min and |eta + y| < eta_max and every pair
 // Delta R > dr_min (bounds <= 0 are off).  eta = atanh(pz/|p|), evaluated as
-// sign(pz) log((|p| + |pz|) / pT), which has no cancellation near the beam;
-// phi = atan2(py, px).  Both with the short functions of fastmath.hpp: they
-// only decide cuts, and a decision can move only for a point within a few
-// ulp of a bound.
+// sign(pz) log((|p| + |pz|)^2 / pT^2) / 2, which has no cancellation near the
+// beam; phi = atan2(py, px).  Both with the short functions of fastmath.hpp,
+// and pT and Delta R compared through their squares: these only decide cuts,
+// and a decision can move only for a point within a few ulp of a bound.
 template <int N>
 __device__ __forceinline__ bool pass_cuts(const Vec4 (&k)[N], double y, double pt_min,
                                           double eta_max, double dr_min)
@@ -75,14 +75,15 @@ __device__ __forceinline__ bool pass_cuts(const Vec4 (&k)[N], double y, double p
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         const double pt2 = k[i].x * k[i].x + k[i].y * k[i].y;
-        const double pt = sqrt(pt2);
         const double pabs = sqrt(pt2 + k[i].z * k[i].z);
-        eta[i] = copysign(fm::log((pabs + fabs(k[i].z)) / pt), k[i].z) + y;
+        const double big = pabs + fabs(k[i].z);
+        eta[i] = copysign(0.5 * fm::log(big * big / pt2), k[i].z) + y;
         phi[i] = fm::atan2(k[i].y, k[i].x);
-        if (pt_min > 0.0) ok = ok && (pt > pt_min);
+        if (pt_min > 0.0) ok = ok && (pt2 > pt_min * pt_min);
         if (eta_max > 0.0) ok = ok && (fabs(eta[i]) < eta_max);
     }
     if (dr_min > 0.0) {
+        const double dr2 = dr_min * dr_min;
 #pragma unroll
         for (int i = 0; i < N; ++i)
 #pragma unroll
@@ -90,7 +91,7 @@ __device__ __forceinline__ bool pass_cuts(const Vec4 (&k)[N], double y, double p
                 const double de = eta[i] - eta[j];
                 double dp = fabs(phi[i] - phi[j]);
                 dp = dp > M_PI ? 2.0 * M_PI - dp : dp;
-                ok = ok && (sqrt(de * de + dp * dp) > dr_min);
+                ok = ok && (de * de + dp * dp > dr2);
             }
     }
     return ok;

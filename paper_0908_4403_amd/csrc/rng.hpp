@@ -23,8 +23,9 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
         // one 32x32->64 multiply gives both halves of each product
         const uint64_t pA = static_cast<uint64_t>(kMulA) * c0;
         const uint64_t pB = static_cast<uint64_t>(kMulB) * c2;
-        const uint32_t t0 = static_cast<uint32_t>(pB >> 32) ^ c1 ^ k0;
-        const uint32_t t2 = static_cast<uint32_t>(pA >> 32) ^ c3 ^ k1;
+        // three-input XOR in one instruction (bit table 0x96: odd number of ones)
+        const uint32_t t0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pB >> 32), c1, k0, 0x96);
+        const uint32_t t2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pA >> 32), c3, k1, 0x96);
         c0 = t0;
         c1 = static_cast<uint32_t>(pB);
         c2 = t2;
