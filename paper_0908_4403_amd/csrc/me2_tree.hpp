@@ -184,6 +184,20 @@ __device__ __forceinline__ Half<R, H> vertex_half(const Vert<R, H> &v, const Cha
     return s;
 }
 
+// s += V' g for every variant, as one chain of fused multiply-adds per
+// component (the pair sums of quad_close).
+template <typename R, int H>
+__device__ __forceinline__ void vertex_half_add(const Vert<R, H> &v, const Chain<R, H> &c, Half<R, H> &s)
+{
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        s.s1r[h] = fma(v.a3[h], c.g2r[h], fma(v.br[h], c.g3r[h], fma(-v.bi[h], c.g3i[h], s.s1r[h])));
+        s.s1i[h] = fma(v.a3[h], c.g2i[h], fma(v.br[h], c.g3i[h], fma(v.bi[h], c.g3r[h], s.s1i[h])));
+        s.s2r[h] = fma(v.gr[h], c.g2r[h], fma(-v.gi[h], c.g2i[h], fma(-v.a3[h], c.g3r[h], s.s2r[h])));
+        s.s2i[h] = fma(v.gr[h], c.g2i[h], fma(v.gi[h], c.g2r[h], fma(-v.a3[h], c.g3i[h], s.s2i[h])));
+    }
+}
+
 // The propagator half: g' = d P(q') (sl1, sl2).
 template <typename R, int H>
 __device__ __forceinline__ void propagator_half(const Prop<R> &P, const Half<R, H> &s, Chain<R, H> &o)
@@ -266,14 +280,11 @@ __device__ __forceinline__ void make_pairs(const Slots<R, H, NS> &S, const LMom<
                 const R x1i = w1i[b][h] * va.a3[h] + w2r[b][h] * va.gi[h] + w2i[b][h] * va.gr[h];
                 const R x2r = w1r[b][h] * va.br[h] - w1i[b][h] * va.bi[h] - w2r[b][h] * va.a3[h];
                 const R x2i = w1r[b][h] * va.bi[h] + w1i[b][h] * va.br[h] - w2i[b][h] * va.a3[h];
-                const R y1r = w1r[a][h] * vb.a3[h] + w2r[a][h] * vb.gr[h] - w2i[a][h] * vb.gi[h];
-                const R y1i = w1i[a][h] * vb.a3[h] + w2r[a][h] * vb.gi[h] + w2i[a][h] * vb.gr[h];
-                const R y2r = w1r[a][h] * vb.br[h] - w1i[a][h] * vb.bi[h] - w2r[a][h] * vb.a3[h];
-                const R y2i = w1r[a][h] * vb.bi[h] + w1i[a][h] * vb.br[h] - w2i[a][h] * vb.a3[h];
-                T.u1r[a][b][h] = x1r + y1r;
-                T.u1i[a][b][h] = x1i + y1i;
-                T.u2r[a][b][h] = x2r + y2r;
-                T.u2i[a][b][h] = x2i + y2i;
+                // + u_ba, continued as fused multiply-adds on u_ab
+                T.u1r[a][b][h] = fma(w1r[a][h], vb.a3[h], fma(w2r[a][h], vb.gr[h], fma(-w2i[a][h], vb.gi[h], x1r)));
+                T.u1i[a][b][h] = fma(w1i[a][h], vb.a3[h], fma(w2r[a][h], vb.gi[h], fma(w2i[a][h], vb.gr[h], x1i)));
+                T.u2r[a][b][h] = fma(w1r[a][h], vb.br[h], fma(-w1i[a][h], vb.bi[h], fma(-w2r[a][h], vb.a3[h], x2r)));
+                T.u2i[a][b][h] = fma(w1r[a][h], vb.bi[h], fma(w1i[a][h], vb.br[h], fma(-w2i[a][h], vb.a3[h], x2i)));
             }
 }
 
@@ -327,14 +338,7 @@ __device__ __forceinline__ void quad_close(const Slots<R, H, NS> &S, const PT &T
         LMom<R> q2;
         const Prop<R> P = propagate<R>(q1[X[t]], S.k[sl[Y[t]]], q2);
         Half<R, H> s = vertex_half<R, H>(S.v[sl[Y[t]]], g1[X[t]]);
-        const Half<R, H> s2 = vertex_half<R, H>(S.v[sl[X[t]]], g1[Y[t]]);
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-            s.s1r[h] += s2.s1r[h];
-            s.s1i[h] += s2.s1i[h];
-            s.s2r[h] += s2.s2r[h];
-            s.s2i[h] += s2.s2i[h];
-        }
+        vertex_half_add<R, H>(S.v[sl[X[t]]], g1[Y[t]], s);
         Chain<R, H> g2;
         propagator_half<R, H>(P, s, g2);
         close_pair<R, H, NS>(T, sl[A[t]], sl[B[t]], g2, acc);
