@@ -138,6 +138,26 @@ def per_n(H, torch, tune):
         print(f"bench: per-n n={n} FP32 {row['fp32']['points_per_s']:.3e} pts/s "
               f"({row['fp32']['frac']:.2f}), FP64 {row['fp64']['points_per_s']:.3e} "
               f"({row['fp64']['frac']:.2f})", file=sys.stderr, flush=True)
+        if n <= 5:
+            # the general-frame evaluator composed from the HELAS library, same points
+            frame = {}
+            for prec, name in ((H.FP32, "fp32"), (H.FP64, "fp64")):
+                fn = min(npts, 1 << 18)
+                sub = mom[:, :fn].contiguous()
+                fout = torch.empty(fn, dtype=torch.float64, device="cuda")
+                H.me2_frame_device(n, sub, fout, prec)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(3):
+                    H.me2_frame_device(n, sub, fout, prec)
+                e1.record()
+                torch.cuda.synchronize()
+                fms = e0.elapsed_time(e1) / 3
+                frame[name] = {"points": fn, "kernel_ms": fms, "points_per_s": fn / (fms * 1e-3)}
+            row["helas_frame"] = frame
+            print(f"bench: per-n n={n} HELAS frame evaluator FP32 {frame['fp32']['points_per_s']:.3e} "
+                  f"pts/s, FP64 {frame['fp64']['points_per_s']:.3e}", file=sys.stderr, flush=True)
         out.append(row)
         del mom, w, me2
     return out

@@ -53,6 +53,7 @@ def lib():
         L = C.CDLL(_build.LIB)
         L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
         L.orc_uniform_pair.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, _dp]
+        L.orc_uniform_quad.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, _dp]
         L.orc_rambo.argtypes = [C.c_int, C.c_double, _dp, _dp]
         L.orc_rambo_weight.argtypes = [C.c_int, C.c_double]
         L.orc_rambo_weight.restype = C.c_double
@@ -115,6 +116,13 @@ def philox(ctr, key) -> np.ndarray:
     lib().orc_philox4x32_10(c.ctypes.data_as(_u32p), k.ctypes.data_as(_u32p),
                             out.ctypes.data_as(_u32p))
     return out
+
+
+def uniform_quad(seed: int, point: int, block: int, stream: int) -> np.ndarray:
+    """Four uniforms, one per 32-bit word of one Philox call (the photons' draws)."""
+    u = np.zeros(4)
+    lib().orc_uniform_quad(seed, point, block, stream, _ptr(u))
+    return u
 
 
 def uniform_pair(seed: int, point: int, block: int, stream: int) -> np.ndarray:

@@ -69,26 +69,28 @@ void orc_uniform_pair(uint64_t seed, uint64_t point, uint32_t block, uint32_t st
     u[1] = u53(r[2], r[3]);
 }
 
+/* Four uniforms in (0,1) from one call, one per 32-bit word: (w + 1/2) 2^-32
+ * (the photons' draws, one call per photon). */
+void orc_uniform_quad(uint64_t seed, uint64_t point, uint32_t block, uint32_t stream,
+                      double u[4])
+{
+    uint32_t ctr[4] = {(uint32_t)point, (uint32_t)(point >> 32), block, stream};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    for (int j = 0; j < 4; ++j) u[j] = ((double)r[j] + 0.5) * 0x1.0p-32;
+}
+
 /* ------------------------------------------------------------------------ */
 /* RAMBO for massless momenta (Kleiss, Stirling, Ellis 1986).                */
 /* ------------------------------------------------------------------------ */
-void orc_rambo(int n, double sqrt_s, const double *u, double *k)
+/* RAMBO's conformal transformation: boost the n vectors q to the rest frame
+ * of their sum Q and rescale so that the sum becomes (sqrt_s, 0, 0, 0). */
+static void conformal_map(int n, double sqrt_s, double q[][4], double *k)
 {
-    double q[8][4];
     double Q[4] = {0, 0, 0, 0};
-    for (int i = 0; i < n; ++i) {
-        /* isotropic direction and energy density q0 exp(-q0) */
-        double c = 2.0 * u[4 * i + 0] - 1.0;
-        double s = sqrt(1.0 - c * c);
-        double f = 2.0 * M_PI * u[4 * i + 1];
-        double e = -log(u[4 * i + 2] * u[4 * i + 3]);
-        q[i][0] = e;
-        q[i][1] = e * s * cos(f);
-        q[i][2] = e * s * sin(f);
-        q[i][3] = e * c;
+    for (int i = 0; i < n; ++i)
         for (int m = 0; m < 4; ++m) Q[m] += q[i][m];
-    }
-    /* conformal transformation: boost to the rest frame of Q and rescale */
     double M = sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
     double b[3] = {-Q[1] / M, -Q[2] / M, -Q[3] / M};
     double x = sqrt_s / M;
@@ -100,6 +102,35 @@ void orc_rambo(int n, double sqrt_s, const double *u, double *k)
         for (int m = 1; m < 4; ++m)
             k[4 * i + m] = x * (q[i][m] + b[m - 1] * q[i][0] + a * bq * b[m - 1]);
     }
+}
+
+void orc_rambo(int n, double sqrt_s, const double *u, double *k)
+{
+    double q[8][4];
+    for (int i = 0; i < n; ++i) {
+        /* isotropic direction and energy density q0 exp(-q0) */
+        double c = 2.0 * u[4 * i + 0] - 1.0;
+        double s = sqrt(1.0 - c * c);
+        double f = 2.0 * M_PI * u[4 * i + 1];
+        double e = -log(u[4 * i + 2] * u[4 * i + 3]);
+        q[i][0] = e;
+        q[i][1] = e * s * cos(f);
+        q[i][2] = e * s * sin(f);
+        q[i][3] = e * c;
+    }
+    conformal_map(n, sqrt_s, q, k);
+    /* The map scales the rounding-level masses of the q's by about the square
+     * of its boost factor, which is large when the q's are nearly collinear.
+     * Put every momentum back on shell (energy = |3-momentum|) and apply the
+     * map once more: it is now a near-identity, so the result is massless and
+     * conserves momentum to rounding.  Exact arithmetic gives the same points. */
+    for (int i = 0; i < n; ++i) {
+        q[i][1] = k[4 * i + 1];
+        q[i][2] = k[4 * i + 2];
+        q[i][3] = k[4 * i + 3];
+        q[i][0] = sqrt(q[i][1] * q[i][1] + q[i][2] * q[i][2] + q[i][3] * q[i][3]);
+    }
+    conformal_map(n, sqrt_s, q, k);
 }
 
 /* Volume of the massless n-body phase space of eq. (4):
@@ -116,10 +147,7 @@ double orc_rambo_weight(int n, double s)
 void orc_cm_event(int n, double sqrt_shat, uint64_t seed, uint64_t point, double *p)
 {
     double u[32];
-    for (int i = 0; i < n; ++i) {
-        orc_uniform_pair(seed, point, (uint32_t)(2 * i), 0, &u[4 * i]);
-        orc_uniform_pair(seed, point, (uint32_t)(2 * i + 1), 0, &u[4 * i + 2]);
-    }
+    for (int i = 0; i < n; ++i) orc_uniform_quad(seed, point, (uint32_t)i, 0, &u[4 * i]);
     double e = 0.5 * sqrt_shat;
     double p1[4] = {e, 0, 0, e}, p2[4] = {e, 0, 0, -e};
     memcpy(p, p1, sizeof p1);

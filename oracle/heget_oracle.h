@@ -35,9 +35,13 @@ extern "C" {
 
 /* ---- counter-based random numbers (Philox4x32-10, Salmon et al., SC'11) ---- */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
-/* Two uniforms in (0,1) for (seed, point, block, stream): counter =
- * {lo32(point), hi32(point), block, stream}, key = {lo32(seed), hi32(seed)};
- * u[0] from words (1:0), u[1] from words (3:2), each (top 53 bits + 1/2) * 2^-53. */
+/* Counter = {lo32(point), hi32(point), block, stream}, key = {lo32(seed),
+ * hi32(seed)}.  orc_uniform_quad: four uniforms in (0,1), one per word,
+ * (w_j + 1/2) * 2^-32 (the photons).  orc_uniform_pair: two uniforms, u[0]
+ * from words (1:0), u[1] from words (3:2), each (top 53 bits + 1/2) * 2^-53
+ * (the partonic kinematics). */
+void orc_uniform_quad(uint64_t seed, uint64_t point, uint32_t block, uint32_t stream,
+                      double u[4]);
 void orc_uniform_pair(uint64_t seed, uint64_t point, uint32_t block, uint32_t stream,
                       double u[2]);
 
@@ -48,7 +52,7 @@ void orc_rambo(int n, double sqrt_s, const double *u, double *k);
 /* constant RAMBO weight = volume of massless n-body phase space of eq. (4) */
 double orc_rambo_weight(int n, double s);
 /* CM event p[n+2][4] at sqrt_shat for point `point` of stream `seed`
- * (u along +z, ubar along -z, photons from RAMBO with stream-0 blocks 0..2n-1). */
+ * (u along +z, ubar along -z, photons from RAMBO with stream-0 blocks 0..n-1). */
 void orc_cm_event(int n, double sqrt_shat, uint64_t seed, uint64_t point, double *p);
 /* points first .. first+np-1 into p_aos[np][n+2][4] (OpenMP) */
 void orc_cm_events(int n, double sqrt_shat, uint64_t seed, uint64_t first, int64_t np,

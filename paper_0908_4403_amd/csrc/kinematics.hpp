@@ -21,24 +21,14 @@ struct Vec4 {
     double e, x, y, z;
 };
 
-// Photon momenta of point `point`: uniforms from stream 0, blocks 2i and 2i+1.
+// RAMBO's conformal transformation in place: boost the N vectors to the rest
+// frame of their sum and rescale the sum to (sqrt_s, 0, 0, 0).
 template <int N>
-__device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t point, Vec4 (&k)[N])
+__device__ __forceinline__ void conformal_map(double sqrt_s, Vec4 (&k)[N])
 {
     double Qe = 0.0, Qx = 0.0, Qy = 0.0, Qz = 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        double ucos, uphi, ue1, ue2;
-        uniform_pair(seed, point, 2u * i, 0u, ucos, uphi);
-        uniform_pair(seed, point, 2u * i + 1u, 0u, ue1, ue2);
-        const double c = 2.0 * ucos - 1.0;
-        const double s = sqrt(1.0 - c * c);
-        // the momenta use the library's sincospi and log, so they agree with
-        // any correctly rounded evaluation to an ulp
-        double sf, cf;
-        sincospi(2.0 * uphi, &sf, &cf);  // azimuth 2 pi uphi
-        const double e = -log(ue1 * ue2);
-        k[i] = {e, e * s * cf, e * s * sf, e * c};
         Qe += k[i].e;
         Qx += k[i].x;
         Qy += k[i].y;
@@ -58,6 +48,35 @@ __device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t poi
         k[i].y = x * (k[i].y + by * e + a * bq * by);
         k[i].z = x * (k[i].z + bz * e + a * bq * bz);
     }
+}
+
+// Photon momenta of point `point`: four uniforms from stream 0, block i, for photon i.
+template <int N>
+__device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t point, Vec4 (&k)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double u[4];
+        uniform_quad(seed, point, static_cast<uint32_t>(i), 0u, u);
+        const double ucos = u[0], uphi = u[1], ue1 = u[2], ue2 = u[3];
+        const double c = 2.0 * ucos - 1.0;
+        const double s = sqrt(1.0 - c * c);
+        // the momenta use the library's sincospi and log, so they agree with
+        // any correctly rounded evaluation to an ulp
+        double sf, cf;
+        sincospi(2.0 * uphi, &sf, &cf);  // azimuth 2 pi uphi
+        const double e = -log(ue1 * ue2);
+        k[i] = {e, e * s * cf, e * s * sf, e * c};
+    }
+    conformal_map<N>(sqrt_s, k);
+    // The map scales the rounding-level masses of the isotropic vectors by
+    // about the square of its boost factor, which is large when they are
+    // nearly collinear.  Put every momentum back on shell and map once more:
+    // now a near-identity, so the result is massless and conserves momentum to
+    // rounding (exact arithmetic gives the same points).
+#pragma unroll
+    for (int i = 0; i < N; ++i) k[i].e = sqrt(k[i].x * k[i].x + k[i].y * k[i].y + k[i].z * k[i].z);
+    conformal_map<N>(sqrt_s, k);
 }
 
 // 1 if every photon has pT > pt_min and |eta + y| < eta_max and every pair

@@ -43,10 +43,31 @@ __device__ __forceinline__ double open_unit(uint32_t lo, uint32_t hi)
     return (static_cast<double>(w >> 11) + 0.5) * 0x1.0p-53;
 }
 
-// Two uniforms for (seed, point, block, stream).  Counter = {lo(point),
-// hi(point), block, stream}, key = {lo(seed), hi(seed)}.  Stream 0 feeds the
-// photons (blocks 2i, 2i+1 for photon i); stream 1 feeds the partonic
-// kinematics (block 0: parton momentum fractions, block 1: sqrt(shat)).
+// Uniform in (0,1) from one 32-bit word: (w + 1/2) 2^-32.
+__device__ __forceinline__ double open_unit32(uint32_t w)
+{
+    return (static_cast<double>(w) + 0.5) * 0x1.0p-32;
+}
+
+// Four uniforms for (seed, point, block, stream), one per word of one call.
+// Counter = {lo(point), hi(point), block, stream}, key = {lo(seed), hi(seed)}.
+// Stream 0 block i feeds photon i (cos theta, azimuth, two for the energy).
+__device__ __forceinline__ void uniform_quad(uint64_t seed, uint64_t point, uint32_t block,
+                                             uint32_t stream, double (&u)[4])
+{
+    const Words4 r = philox4x32_10(static_cast<uint32_t>(point),
+                                   static_cast<uint32_t>(point >> 32), block, stream,
+                                   static_cast<uint32_t>(seed),
+                                   static_cast<uint32_t>(seed >> 32));
+    u[0] = open_unit32(r.w0);
+    u[1] = open_unit32(r.w1);
+    u[2] = open_unit32(r.w2);
+    u[3] = open_unit32(r.w3);
+}
+
+// Two uniforms of 53 bits for (seed, point, block, stream), same counter and
+// key.  Stream 1 feeds the partonic kinematics (block 0: parton momentum
+// fractions, block 1: sqrt(shat)).
 __device__ __forceinline__ void uniform_pair(uint64_t seed, uint64_t point, uint32_t block,
                                              uint32_t stream, double &u0, double &u1)
 {
