@@ -86,8 +86,8 @@ __device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t poi
 // and pT and Delta R compared through their squares: these only decide cuts,
 // and a decision can move only for a point within a few ulp of a bound.
 template <int N>
-__device__ __forceinline__ bool pass_cuts(const Vec4 (&k)[N], double y, double pt_min,
-                                          double eta_max, double dr_min)
+__device__ __forceinline__ bool pass_cuts_fp64(const Vec4 (&k)[N], double y, double pt_min,
+                                               double eta_max, double dr_min)
 {
     double eta[N], phi[N];
     bool ok = true;
@@ -114,6 +114,76 @@ __device__ __forceinline__ bool pass_cuts(const Vec4 (&k)[N], double y, double p
             }
     }
     return ok;
+}
+
+// The eta and Delta R parts of the same decision in FP32: 1 (pass), 0 (fail),
+// or -1 when an eta lies within kEtaScreen of +-eta_max or a Delta R^2 within
+// kDr2Screen of dr_min^2, where the FP32 values (about 2e-6 from the FP64 ones
+// in eta up to |eta| = 5, 5e-5 in Delta R^2) could sit on the other side.
+// pT is compared in FP64 (it is cheap).  Outside the bands the two
+// evaluations agree, so the screen changes no decision, only its cost.
+constexpr float kEtaScreen = 1e-4f;
+constexpr float kDr2Screen = 1e-3f;
+
+template <int N>
+__device__ __forceinline__ int screen_cuts(const Vec4 (&k)[N], double y, double pt_min,
+                                           double eta_max, double dr_min)
+{
+    float eta[N], phi[N];
+    bool ok = true, unsure = false;
+    const float ln2_half = 0.34657359f;  // ln(2) / 2
+    const float pi = 3.14159265f, half_pi = 1.57079633f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double pt2 = k[i].x * k[i].x + k[i].y * k[i].y;
+        if (pt_min > 0.0) ok = ok && (pt2 > pt_min * pt_min);
+        const float x = static_cast<float>(k[i].x), yy = static_cast<float>(k[i].y);
+        const float z = static_cast<float>(k[i].z);
+        const float p2 = x * x + yy * yy;
+        const float big = __builtin_sqrtf(p2 + z * z) + fabsf(z);
+        // eta = sign(z) ln(big^2 / pT^2) / 2, through the hardware log2
+        eta[i] = copysignf(ln2_half * __builtin_amdgcn_logf(big * big * __builtin_amdgcn_rcpf(p2)), z) +
+                 static_cast<float>(y);
+        // phi by octant reduction and atan on [0, 1]
+        const float ax = fabsf(x), ay = fabsf(yy);
+        const bool swap = ay > ax;
+        const float t = (swap ? ax : ay) * __builtin_amdgcn_rcpf(swap ? ay : ax);
+        float a = fm::atan_unit_f(t);
+        a = swap ? half_pi - a : a;
+        a = x < 0.0f ? pi - a : a;
+        phi[i] = copysignf(a, yy);
+        if (eta_max > 0.0) {
+            const float d = fabsf(eta[i]) - static_cast<float>(eta_max);
+            ok = ok && (d < 0.0f);
+            unsure = unsure || (fabsf(d) < kEtaScreen);
+        }
+    }
+    if (dr_min > 0.0) {
+        const float dr2 = static_cast<float>(dr_min * dr_min);
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = i + 1; j < N; ++j) {
+                const float de = eta[i] - eta[j];
+                float dp = fabsf(phi[i] - phi[j]);
+                dp = dp > pi ? 2.0f * pi - dp : dp;
+                const float d = de * de + dp * dp - dr2;
+                ok = ok && (d > 0.0f);
+                unsure = unsure || (fabsf(d) < kDr2Screen);
+            }
+    }
+    return unsure ? -1 : (ok ? 1 : 0);
+}
+
+// The cut decision: the FP32 screen, and the FP64 evaluation only for points
+// the screen leaves open.
+template <int N>
+__device__ __forceinline__ bool pass_cuts(const Vec4 (&k)[N], double y, double pt_min,
+                                          double eta_max, double dr_min)
+{
+    const int s = screen_cuts<N>(k, y, pt_min, eta_max, dr_min);
+    if (s >= 0) return s == 1;
+    return pass_cuts_fp64<N>(k, y, pt_min, eta_max, dr_min);
 }
 
 // Kinematic parameters shared by every point of one generation call.

@@ -83,7 +83,13 @@ int main() {
     bad += std::fabs(heget::fm::atan2(1.0, 0.0) - 1.5707963267948966) > 0;
     bad += std::fabs(heget::fm::atan2(0.0, -1.0) - 3.141592653589793) > 0;
     bad += std::fabs(heget::fm::atan2(-0.0, -1.0) + 3.141592653589793) > 0;
-    std::printf("%.3f %.3f %.3f %.3f %d\n", worst_log, worst_sin, worst_cos, worst_atan, bad);
+    // FP32 atan on [0, 1] of the cut screen: absolute error in radians
+    double worst_atanf = 0;
+    for (int i = 0; i <= 1000000; ++i) {
+        const float t = (float)(i * 1e-6);
+        worst_atanf = std::fmax(worst_atanf, std::fabs((double)heget::fm::atan_unit_f(t) - std::atan((double)t)));
+    }
+    std::printf("%.3f %.3f %.3f %.3f %d %.3e\n", worst_log, worst_sin, worst_cos, worst_atan, bad, worst_atanf);
     return 0;
 }
 """
@@ -98,7 +104,7 @@ def errors(tmp_path_factory):
     subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-I", CSRC, str(src), "-o", str(exe)],
                    check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
-    return [float(v) for v in out[:4]] + [int(out[4])]
+    return [float(v) for v in out[:4]] + [int(out[4]), float(out[5])]
 
 
 def test_log_within_a_few_ulp(errors):
@@ -115,3 +121,9 @@ def test_atan2_within_a_few_ulp(errors):
 
 def test_special_values(errors):
     assert errors[4] == 0, errors
+
+
+def test_fp32_atan_of_the_cut_screen(errors):
+    """The screen assumes phi within a few 1e-7 rad: the polynomial (2e-8) plus
+    FP32 rounding."""
+    assert errors[5] <= 3e-7, errors
