@@ -43,20 +43,28 @@ def _workloads():
     return WORKLOADS, MIXED_BATCH
 
 
-def run_steps(H, torch, n, cfg, steps, warmup):
-    """Enqueue `steps` full passes back to back on the current stream; each writes
-    its result record into its own slot of a device buffer (no host callback).
-    The step time is taken without per-kernel events (an event record stalls
-    the stream by a few microseconds); the amplitude kernel is then timed over
-    as many further passes with HIP events on the launch stream."""
+def run_steps(H, torch, n, cfg, steps, warmup, nstreams=1):
+    """Enqueue `steps` full passes back to back, step k on stream k mod nstreams
+    (the library keeps one scratch set per stream, so passes on different
+    streams are independent and the next pass's generation can fill the issue
+    slots the current pass's amplitude kernel and small kernels leave idle);
+    each writes its result record into its own slot of a device buffer (no
+    host callback).  The step time is taken without per-kernel events (an
+    event record stalls the stream by a few microseconds); the amplitude kernel
+    is then timed over as many further passes, on one stream, with HIP events
+    on the launch stream."""
     total = warmup + 2 * steps
     buf = torch.zeros((total, 64), dtype=torch.uint8, device="cuda")
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(nstreams - 1)]
+    # every stream's first pass sizes its scratch set: keep that out of the timing
+    for s in streams[warmup:]:
+        H.xsec_device(n, cfg, buf[0], stream=s)
     for k in range(warmup):
-        H.xsec_device(n, cfg, buf[k])
+        H.xsec_device(n, cfg, buf[k], stream=streams[k % nstreams])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(warmup, warmup + steps):
-        H.xsec_device(n, cfg, buf[k])
+        H.xsec_device(n, cfg, buf[k], stream=streams[k % nstreams])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     H.timing_enable(True)
@@ -200,6 +208,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed n=2..7 batch")
     ap.add_argument("--no-tune", action="store_true", help="use the untuned kernel shapes")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="consecutive steps go to this many streams in turn (1: one stream)")
     ap.add_argument("--per-n", action="store_true",
                     help="also time the amplitude kernel alone for n = 2..8 (FP32 and FP64)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -234,11 +244,17 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    print(f"bench: {args.workload} FP32 steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
-    ms32, k32, l32, r32 = run_steps(H, torch, n, H.Config(prec=H.FP32, **base), args.steps, args.warmup)
-    print(f"bench: FP32 {ms32:.3f} ms/step, me2 kernel {k32:.3f} ms", file=sys.stderr, flush=True)
+    print(f"bench: {args.workload} FP32 steps={args.steps} warmup={args.warmup} streams={args.streams}",
+          file=sys.stderr, flush=True)
+    ms32, k32, l32, r32 = run_steps(H, torch, n, H.Config(prec=H.FP32, **base), args.steps, args.warmup,
+                                    args.streams)
+    ms32_one = ms32
+    if args.streams > 1:
+        ms32_one = run_steps(H, torch, n, H.Config(prec=H.FP32, **base), args.steps, 1, 1)[0]
+    print(f"bench: FP32 {ms32:.3f} ms/step ({ms32_one:.3f} on one stream), me2 kernel {k32:.3f} ms",
+          file=sys.stderr, flush=True)
     ms64, k64, l64, r64 = run_steps(H, torch, n, H.Config(prec=H.FP64, **base),
-                                    max(3, args.steps // 2), 1)
+                                    max(3, args.steps // 2), 1, args.streams)
     print(f"bench: FP64 {ms64:.3f} ms/step, me2 kernel {k64:.3f} ms", file=sys.stderr, flush=True)
 
     n_acc = r32["n_acc"]
@@ -283,6 +299,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "process": f"u ubar -> {n} photons",
+                   "streams": args.streams, "ms_per_step_one_stream": ms32_one,
                    "sqrt_shat_GeV": wl["sqrt_s"], "points_generated": wl["npoints"],
                    "points_evaluated": n_acc, "seed": wl["seed"],
                    "cuts": "pT>%g GeV, |eta|<%g, dR>%g" % tuple(wl["cuts"]), "sigma_fb": r32["sigma_fb"],
