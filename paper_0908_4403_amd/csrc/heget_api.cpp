@@ -86,7 +86,7 @@ State g;
 constexpr int kRing = 256;
 
 enum Slot {
-    S_MOM, S_WFAC, S_FLAG, S_BCOUNT, S_OFFS, S_COUNT, S_INDEX, S_PART, S_PARTIALS, S_RES, S_FLAGS,
+    S_MOM, S_WFAC, S_FLAG, S_BCOUNT, S_COUNT, S_INDEX, S_PART, S_PARTIALS, S_RES, S_FLAGS,
     S_OUT, S_BATCH, S_HEL, S_WOUT, S_BINS, S_HIST, S_NSLOTS
 };
 
@@ -562,7 +562,7 @@ void xsec_finish(void *p)
 struct McBufs {
     double *mom, *wfac, *part, *partials, *res;
     uint8_t *flag;
-    int32_t *bcount, *offs, *index;
+    int32_t *bcount, *index;
     uint16_t *hel;  // sampled helicity configurations, or nullptr (helicity sum)
     double *wout;   // per-survivor weights (histograms), or nullptr
     int64_t *d_count;
@@ -608,8 +608,7 @@ heget_status enqueue_generation(int n, const heget_config &c, const McBufs &b, h
     gp.clear_word = clear;
     gp.hel_out = b.hel;
     HG_HIP(heget::launch_gen(n, gp, b.mom, np, b.wfac, b.flag, b.bcount, s));
-    HG_HIP(heget::launch_scan(b.bcount, static_cast<int>((np + 255) / 256), b.offs, b.d_count, s));
-    HG_HIP(heget::launch_compact(b.flag, np, b.offs, b.index, s));
+    HG_HIP(heget::launch_compact(b.flag, np, b.bcount, b.index, b.d_count, s));
     return HEGET_OK;
 }
 
@@ -666,7 +665,6 @@ heget_status xsec_enqueue(int n, const heget_config *cfg, heget_result *out, heg
     HG_TRY(scratch_t<double>(S_WFAC, size_t(np), &b.wfac));
     HG_TRY(scratch_t<uint8_t>(S_FLAG, size_t(np), &b.flag));
     HG_TRY(scratch_t<int32_t>(S_BCOUNT, size_t(nb), &b.bcount));
-    HG_TRY(scratch_t<int32_t>(S_OFFS, size_t(nb), &b.offs));
     HG_TRY(scratch_t<int64_t>(S_COUNT, 1, &b.d_count));
     HG_TRY(scratch_t<int32_t>(S_INDEX, size_t(np), &b.index));
     b.hel = nullptr;
@@ -752,7 +750,6 @@ void carve_batch(Arena &ar, int ncfg, const int *n, const heget_config *cfgs, in
         b.wfac = ar.take<double>(size_t(np));
         b.flag = ar.take<uint8_t>(size_t(np));
         b.bcount = ar.take<int32_t>(size_t((np + 255) / 256));
-        b.offs = ar.take<int32_t>(size_t((np + 255) / 256));
         b.index = ar.take<int32_t>(size_t(np));
         b.hel = nullptr;
         b.wout = nullptr;

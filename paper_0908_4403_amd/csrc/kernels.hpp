@@ -85,12 +85,10 @@ void me2_batch_shape(int prec, int n, int *mb, int *h, int *cl);
 // count per block of 256 points.
 hipError_t launch_gen(int n, const GenParams &g, double *mom, int64_t ld, double *w,
                       uint8_t *flag, int32_t *block_count, hipStream_t stream);
-// Exclusive scan of nb block counts -> offsets, total -> *d_count.
-hipError_t launch_scan(const int32_t *counts, int nb, int32_t *offsets, int64_t *d_count,
-                       hipStream_t stream);
-// Survivor list: index[offsets[b] + rank] = point, in point order.
-hipError_t launch_compact(const uint8_t *flag, int64_t np, const int32_t *offsets,
-                          int32_t *index, hipStream_t stream);
+// Survivor list: index[offset_b + rank] = point, in point order, with the
+// offsets summed from the per-block counts; the survivor total -> *d_count.
+hipError_t launch_compact(const uint8_t *flag, int64_t np, const int32_t *counts, int32_t *index,
+                          int64_t *d_count, hipStream_t stream);
 
 // Sum of helicity chunks: out[k] = sum_c part[c*ld + k]; with `partials`, the
 // per-tile weighted triples of sum_c part * wfac[index[k]] instead (as the

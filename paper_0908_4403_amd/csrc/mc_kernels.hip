@@ -3,8 +3,8 @@
 // eq. (1)-(2) are applied in the amplitude pass; a deterministic compensated
 // reduction gives sigma and its error.  All FP64.
 //
-// Determinism: compaction keeps point order (block counts -> exclusive scan
-// -> in-block ballot ranks), and every sum is a fixed tree (64-point tiles by
+// Determinism: compaction keeps point order (block counts -> each block's
+// offset summed from its predecessors' counts -> in-block ballot ranks), and every sum is a fixed tree (64-point tiles by
 // xor shuffles, tiles in index order), so a configuration gives bitwise the
 // same sigma on every run.
 #include <hip/hip_runtime.h>
@@ -78,50 +78,46 @@ gen_kernel(GenParams g, double *__restrict__ mom, int64_t ld, double *__restrict
     }
 }
 
-// Exclusive scan of nb counts by one block of 1024 threads.
-__global__ void __launch_bounds__(1024)
-scan_kernel(const int32_t *__restrict__ counts, int nb, int32_t *__restrict__ offsets,
-            int64_t *__restrict__ total)
-{
-    __shared__ int64_t part[1024];
-    const int t = threadIdx.x;
-    const int per = (nb + 1023) / 1024;
-    const int beg = min(t * per, nb), end = min(beg + per, nb);
-    int64_t s = 0;
-    for (int j = beg; j < end; ++j) s += counts[j];
-    part[t] = s;
-    __syncthreads();
-    // inclusive Hillis-Steele scan over the 1024 partial sums
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int64_t v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int64_t run = part[t] - s;
-    for (int j = beg; j < end; ++j) {
-        offsets[j] = static_cast<int32_t>(run);
-        run += counts[j];
-    }
-    if (t == 1023) *total = part[1023];
-}
-
-// Survivor list: index[offsets[b] + rank] = point, in point order.
+// Survivor list: index[offset_b + rank] = point, in point order, where block b
+// (256 points) finds offset_b, the survivors of blocks 0..b-1, by summing
+// their counts itself (at most a few KiB of L2-resident reads per block, so
+// no separate scan pass); the last block writes the total to *d_count.
 __global__ void __launch_bounds__(256)
-compact_kernel(const uint8_t *__restrict__ flag, int64_t np, const int32_t *__restrict__ offsets,
-               int32_t *__restrict__ index)
+compact_kernel(const uint8_t *__restrict__ flag, int64_t np, const int32_t *__restrict__ counts,
+               int nb, int32_t *__restrict__ index, int64_t *__restrict__ d_count)
 {
+    __shared__ int part[4];
     __shared__ int wave_count[4];
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    // offset: the counts of blocks 0..b-1, four per 16-byte load (the count
+    // buffer is 256-byte aligned), loads batched so their latencies overlap
+    const int b = static_cast<int>(blockIdx.x);
+    const int4 *c4 = reinterpret_cast<const int4 *>(counts);
+    const int nfull = b >> 2;
+    int s = 0;
+#pragma unroll 4
+    for (int j = t; j < nfull; j += 256) {
+        const int4 v = c4[j];
+        s += (v.x + v.y) + (v.z + v.w);
+    }
+    if (t < b - (nfull << 2)) s += counts[(nfull << 2) + t];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + t;
     const bool f = i < np && flag[i] != 0;
-    const uint64_t b = __ballot(f);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int rank = __popcll(b & ((1ull << lane) - 1ull));
-    if (lane == 0) wave_count[w] = __popcll(b);
+    const uint64_t bal = __ballot(f);
+    const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) {
+        part[w] = s;
+        wave_count[w] = __popcll(bal);
+    }
     __syncthreads();
-    int base = offsets[blockIdx.x];
+    const int offset = part[0] + part[1] + part[2] + part[3];
+    int base = offset;
     for (int k = 0; k < w; ++k) base += wave_count[k];
     if (f) index[base + rank] = static_cast<int32_t>(i);
+    if (t == 0 && b == nb - 1)
+        *d_count = offset + wave_count[0] + wave_count[1] + wave_count[2] + wave_count[3];
 }
 
 // ---------------------------------------------------------------- sums
@@ -358,20 +354,13 @@ hipError_t launch_gen(int n, const GenParams &g, double *mom, int64_t ld, double
     }
 }
 
-hipError_t launch_scan(const int32_t *counts, int nb, int32_t *offsets, int64_t *d_count,
-                       hipStream_t stream)
-{
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, counts, nb, offsets, d_count);
-    return hipGetLastError();
-}
-
-hipError_t launch_compact(const uint8_t *flag, int64_t np, const int32_t *offsets, int32_t *index,
-                          hipStream_t stream)
+hipError_t launch_compact(const uint8_t *flag, int64_t np, const int32_t *counts, int32_t *index,
+                          int64_t *d_count, hipStream_t stream)
 {
     const int64_t blocks = (np + 255) / 256;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(compact_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
-                       flag, np, offsets, index);
+                       flag, np, counts, static_cast<int>(blocks), index, d_count);
     return hipGetLastError();
 }
 
