@@ -341,7 +341,33 @@ __device__ __forceinline__ void quad_close(const Slots<R, H, NS> &S, const PT &T
         vertex_half_add<R, H>(S.v[sl[X[t]]], g1[Y[t]], s);
         Chain<R, H> g2;
         propagator_half<R, H>(P, s, g2);
-        close_pair<R, H, NS>(T, sl[A[t]], sl[B[t]], g2, acc);
+        // FP64 products pay off where a split's conversions are shared by
+        // many configurations (and always in FP64, where there are none)
+        if constexpr (std::is_same<R, double>::value || H >= 8)
+            close_pair_wide<R, H, NS>(T, sl[A[t]], sl[B[t]], g2, acc);
+        else
+            close_pair<R, H, NS>(T, sl[A[t]], sl[B[t]], g2, acc);
+    }
+}
+
+// Close a node with slots a < b left as close_pair does, with the product
+// taken in FP64: the FP32 factors convert exactly and every product of two
+// is exact in FP64, so each split enters the FP64 ordering sum through fused
+// multiply-adds, with no FP32 rounding of its own.  In quad_close the
+// conversions of the four pair vectors and four currents of a split are
+// shared by up to sixteen helicity configurations, which makes this cheaper
+// than an FP32 product followed by a conversion and an FP64 add.
+template <typename R, int H, int NS>
+__device__ __forceinline__ void close_pair_wide(const PairTab<R, H, NS> &T, int a, int b,
+                                                const Chain<R, H> &c, Acc<H> &acc)
+{
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const double u1r = T.u1r[a][b][h], u1i = T.u1i[a][b][h];
+        const double u2r = T.u2r[a][b][h], u2i = T.u2i[a][b][h];
+        const double g2r = c.g2r[h], g2i = c.g2i[h], g3r = c.g3r[h], g3i = c.g3i[h];
+        acc.re[h] = fma(u1r, g2r, fma(-u1i, g2i, fma(u2r, g3r, fma(-u2i, g3i, acc.re[h]))));
+        acc.im[h] = fma(u1r, g2i, fma(u1i, g2r, fma(u2r, g3i, fma(u2i, g3r, acc.im[h]))));
     }
 }
 

@@ -110,6 +110,23 @@ def test_xsec_matches_oracle_same_sample(H, orc, n, mode, extra, npoints):
         assert abs(got["sigma_fb"] / want["sigma_fb"] - 1) < tol
 
 
+@pytest.mark.parametrize("npoints", [1, 255, 256, 257, 1023, 4097])
+def test_compaction_edges_match_oracle(H, orc, npoints):
+    """Survivor counts and sigma across block edges (256-point blocks, the
+    offsets summed four counts per load plus a remainder), with cuts that
+    keep some, none and all of the points."""
+    for pt_min, eta_max, dr_min in ((20.0, 2.5, 0.4), (600.0, 2.5, 0.4), (0.0, 0.0, 0.0)):
+        kw = dict(seed=21, npoints=npoints, sqrt_s=1000.0, pt_min=pt_min, eta_max=eta_max, dr_min=dr_min)
+        hc, oc = _cfgs(H, orc, H.FIXED_SHAT, prec=H.FP64, **kw)
+        got = H.xsec(3, hc)
+        want = orc.xsec(3, oc)
+        assert got["n_gen"] == npoints and got["n_acc"] == want["n_acc"], (pt_min, got, want)
+        if want["n_acc"] == 0:
+            assert got["sigma_fb"] == 0.0
+        else:
+            assert abs(got["sigma_fb"] / want["sigma_fb"] - 1) < 1e-10
+
+
 def test_xsec_deterministic_and_empty(H):
     cfg = H.Config(prec=H.FP32, seed=5, npoints=50000 + 3, sqrt_s=1000.0)
     a = H.xsec(4, cfg)
