@@ -22,7 +22,8 @@ struct Vec4 {
 };
 
 // RAMBO's conformal transformation in place: boost the N vectors to the rest
-// frame of their sum and rescale the sum to (sqrt_s, 0, 0, 0).
+// frame of their sum Q and rescale the sum to (sqrt_s, 0, 0, 0).  1/M and
+// 1/(1 + gamma) = M/(M + Q0) both come from the one quotient 1/(M (M + Q0)).
 template <int N>
 __device__ __forceinline__ void conformal_map(double sqrt_s, Vec4 (&k)[N])
 {
@@ -35,10 +36,12 @@ __device__ __forceinline__ void conformal_map(double sqrt_s, Vec4 (&k)[N])
         Qz += k[i].z;
     }
     const double M = sqrt(Qe * Qe - Qx * Qx - Qy * Qy - Qz * Qz);
-    const double bx = -Qx / M, by = -Qy / M, bz = -Qz / M;
-    const double x = sqrt_s / M;
-    const double gam = Qe / M;
-    const double a = 1.0 / (1.0 + gam);
+    const double r = 1.0 / (M * (M + Qe));
+    const double inv_m = (M + Qe) * r;
+    const double bx = -Qx * inv_m, by = -Qy * inv_m, bz = -Qz * inv_m;
+    const double x = sqrt_s * inv_m;
+    const double gam = Qe * inv_m;
+    const double a = M * M * r;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         const double bq = bx * k[i].x + by * k[i].y + bz * k[i].z;
@@ -47,6 +50,34 @@ __device__ __forceinline__ void conformal_map(double sqrt_s, Vec4 (&k)[N])
         k[i].x = x * (k[i].x + bx * e + a * bq * bx);
         k[i].y = x * (k[i].y + by * e + a * bq * by);
         k[i].z = x * (k[i].z + bz * e + a * bq * bz);
+    }
+}
+
+// The same map for a sum Q = (sqrt_s + d0, d) within rounding of
+// (sqrt_s, 0, 0, 0), to first order in d / sqrt_s: beta = -d / sqrt_s,
+// gamma = 1 and x = 1 - d0 / sqrt_s.  The terms left out are of order
+// (d / sqrt_s)^2 relative, far below one rounding.
+template <int N>
+__device__ __forceinline__ void rebalance(double sqrt_s, Vec4 (&k)[N])
+{
+    double Qe = 0.0, Qx = 0.0, Qy = 0.0, Qz = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        Qe += k[i].e;
+        Qx += k[i].x;
+        Qy += k[i].y;
+        Qz += k[i].z;
+    }
+    const double inv = 1.0 / sqrt_s;
+    const double x = 1.0 - (Qe - sqrt_s) * inv;
+    const double bx = -Qx * inv, by = -Qy * inv, bz = -Qz * inv;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double e = k[i].e;
+        k[i].e = x * (e + (bx * k[i].x + by * k[i].y + bz * k[i].z));
+        k[i].x = x * fma(bx, e, k[i].x);
+        k[i].y = x * fma(by, e, k[i].y);
+        k[i].z = x * fma(bz, e, k[i].z);
     }
 }
 
@@ -61,11 +92,9 @@ __device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t poi
         const double ucos = u[0], uphi = u[1], ue1 = u[2], ue2 = u[3];
         const double c = 2.0 * ucos - 1.0;
         const double s = sqrt(1.0 - c * c);
-        // the momenta use the library's sincospi and log, so they agree with
-        // any correctly rounded evaluation to an ulp
         double sf, cf;
-        sincospi(2.0 * uphi, &sf, &cf);  // azimuth 2 pi uphi
-        const double e = -log(ue1 * ue2);
+        fm::sincospi(2.0 * uphi, &sf, &cf);  // azimuth 2 pi uphi
+        const double e = -fm::log(ue1 * ue2);
         k[i] = {e, e * s * cf, e * s * sf, e * c};
     }
     conformal_map<N>(sqrt_s, k);
@@ -76,7 +105,7 @@ __device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t poi
     // rounding (exact arithmetic gives the same points).
 #pragma unroll
     for (int i = 0; i < N; ++i) k[i].e = sqrt(k[i].x * k[i].x + k[i].y * k[i].y + k[i].z * k[i].z);
-    conformal_map<N>(sqrt_s, k);
+    rebalance<N>(sqrt_s, k);
 }
 
 // 1 if every photon has pT > pt_min and |eta + y| < eta_max and every pair
@@ -229,15 +258,17 @@ struct PointKin {
     bool above;    // PP: sqrt(shat) >= lo
 };
 
-// Partonic kinematics of point `point` (stream 1 of the generator).
+// Partonic kinematics of point `point` (stream 1 of the generator) in mode
+// MODE (heget_mode: 0 fixed, 1 uniform, 2 proton-proton).
+template <int MODE>
 __device__ __forceinline__ PointKin point_kinematics(const GenParams &g, uint64_t point)
 {
     PointKin pk{g.sqrt_s, 0.0, 1.0, true};
-    if (g.mode == 1) {
+    if constexpr (MODE == 1) {
         double r0, r1;
         uniform_pair(g.seed, point, 1u, 1u, r0, r1);
         pk.sqrt_shat = g.lo + (g.hi - g.lo) * r0;
-    } else if (g.mode == 2) {
+    } else if constexpr (MODE == 2) {
         // x = r^(1/a) samples a x^(a-1); the weight D(x) / (a x^(a-1)) keeps
         // only the smooth (1-x)^b factor: a = 0.5 for u, 0.7 for ubar.
         double r0, r1;

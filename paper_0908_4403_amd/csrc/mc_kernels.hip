@@ -15,12 +15,12 @@
 
 namespace heget {
 
-// Kinematics, cut decision and weight of one point.
-template <int N>
+// Kinematics, cut decision and weight of one point in mode MODE.
+template <int N, int MODE>
 __device__ __forceinline__ void point_setup(const GenParams &g, uint64_t point, Vec4 (&k)[N],
                                             double &e_beam, double &w, bool &acc)
 {
-    const PointKin pk = point_kinematics(g, point);
+    const PointKin pk = point_kinematics<MODE>(g, point);
     rambo<N>(pk.sqrt_shat, g.seed, point, k);
     acc = pk.above && pass_cuts<N>(k, pk.y, g.pt_min, g.eta_max, g.dr_min);
     e_beam = 0.5 * pk.sqrt_shat;
@@ -55,7 +55,7 @@ __device__ __forceinline__ void store_point(double *__restrict__ mom, int64_t ld
 
 // Every point, in point order; rejected points keep their momenta, weight 0.
 // Optionally the accept flag per point and the accept count per block of 256.
-template <int N>
+template <int N, int MODE>
 __global__ void __launch_bounds__(256)
 gen_kernel(GenParams g, double *__restrict__ mom, int64_t ld, double *__restrict__ wout,
            uint8_t *__restrict__ flag, int32_t *__restrict__ block_count)
@@ -66,7 +66,7 @@ gen_kernel(GenParams g, double *__restrict__ mom, int64_t ld, double *__restrict
     if (i < g.npoints) {
         Vec4 k[N];
         double e, w;
-        point_setup<N>(g, static_cast<uint64_t>(g.first + i), k, e, w, acc);
+        point_setup<N, MODE>(g, static_cast<uint64_t>(g.first + i), k, e, w, acc);
         store_point<N>(mom, ld, i, e, k);
         wout[i] = acc ? w : 0.0;
         if (flag) flag[i] = acc ? 1 : 0;
@@ -334,8 +334,10 @@ static hipError_t gen_n(const GenParams &g, double *mom, int64_t ld, double *w, 
 {
     const int64_t blocks = (g.npoints + 255) / 256;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(gen_kernel<N>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, g,
-                       mom, ld, w, flag, block_count);
+    // one kernel per partonic mode: the fixed-energy one needs far fewer registers
+    const auto kern = g.mode == 1 ? gen_kernel<N, 1> : g.mode == 2 ? gen_kernel<N, 2> : gen_kernel<N, 0>;
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, g, mom, ld,
+                       w, flag, block_count);
     return hipGetLastError();
 }
 

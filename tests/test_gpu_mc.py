@@ -61,6 +61,23 @@ def test_gen_points_match_oracle(H, orc, n, sqrt_s, seed):
     assert mismatches <= 1
 
 
+@pytest.mark.parametrize("n", [2, 4, 8])
+def test_gen_points_massless_and_conserving(H, n):
+    """The device generator's photons are massless and balance the beams to
+    rounding on many points, nearly collinear seeds included (the oracle's
+    own pins bound the same defects)."""
+    sqrt_s, N = 1000.0, 1 << 16
+    mom, _ = H.gen_points(n, sqrt_s, None, 21, N)
+    k = mom[:, 2:, :]
+    e = k[..., 0]
+    mass = np.abs(e ** 2 - (k[..., 1:] ** 2).sum(axis=-1)) / e ** 2
+    tot = k.sum(axis=1) - np.array([sqrt_s, 0.0, 0.0, 0.0])
+    print(f"n={n} max mass defect {mass.max():.1e}, max imbalance {np.abs(tot).max() / sqrt_s:.1e}",
+          flush=True)
+    assert mass.max() <= 4e-15
+    assert np.abs(tot).max() <= 4e-15 * sqrt_s * n
+
+
 def test_gen_points_device_offsets(H, orc):
     import torch
     n, N, first = 3, 1000, 12345
