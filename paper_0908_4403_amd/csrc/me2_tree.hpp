@@ -304,6 +304,10 @@ __device__ __forceinline__ void close_pair(const PairTab<R, H, NS> &T, int a, in
     }
 }
 
+template <typename R, int H, int NS>
+__device__ __forceinline__ void close_pair_wide(const PairTab<R, H, NS> &T, int a, int b,
+                                                const Chain<R, H> &c, Acc<H> &acc);
+
 // The last four photons of every ordering below a node (slots in MASK,
 // four of them) with pair sums at both ends (CL = 3).  The 24 orderings
 // (x, y, a, b) group by the split {x, y} | {a, b}: the u end contributes the

@@ -14,6 +14,13 @@ HBM bytes per launch of the kernel.
     python -m paper_0908_4403_amd.profiling trace --trace kernel_trace.csv \\
         --out profiles/NAME.md --command "..." [--title "..."]
 
+    python -m paper_0908_4403_amd.profiling issue --pmc passA/ passB/ ... \\
+        --out profiles/NAME.md --command "..." [--title "..."]
+
+The issue summary averages every SQ counter per dispatch (largest grid of
+each kernel) and relates VALU issue to that of the FMA probe kernel, which
+issues one VALU instruction in every cycle it can.
+
 The traffic summary records a digest of the device sources (csrc/); a
 consumer treats the figure as stale (None) once the sources differ.
 """
@@ -142,6 +149,60 @@ def read_traffic(md_path: str, kernel: str):
     return float(b.group(1))
 
 
+PROBE_KERNEL = "fma_peak_kernel<float>"
+ISSUE_KERNELS = ("me2_kernel", "gen_kernel", "compact_kernel", "final_kernel", "fma_peak_kernel")
+
+
+def issue(pmc_dirs):
+    """{short kernel name: {counter: mean per dispatch}} over the given counter
+    passes, for the largest-grid dispatches of the kernels of the path."""
+    sums = {}
+    for d in pmc_dirs:
+        rows = read_counters(d)
+        gmax = {}
+        for k, g, c, v in rows:
+            s = short_name(k)
+            if s.split("<")[0] in ISSUE_KERNELS:
+                gmax[s] = max(gmax.get(s, 0), g)
+        for k, g, c, v in rows:
+            s = short_name(k)
+            if s in gmax and g == gmax[s]:
+                t = sums.setdefault(s, {}).setdefault(c, [0.0, 0])
+                t[0] += v
+                t[1] += 1
+    return {k: {c: t[0] / t[1] for c, t in cs.items()} for k, cs in sums.items()}
+
+
+def issue_markdown(stats: dict, command: str, title: str) -> str:
+    counters = sorted({c for cs in stats.values() for c in cs})
+    probe = stats.get(PROBE_KERNEL, {})
+
+    def ratio(cs, a, b):
+        return cs[a] / cs[b] if a in cs and cs.get(b) else None
+
+    ref = ratio(probe, "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES")
+    lines = [f"# {title}", "", "Commands (GPU box, from the repository root):", "", "    " + command, "",
+             "Mean per dispatch (largest launch of each kernel). VALU issue = (SQ_ACTIVE_INST_VALU / "
+             f"SQ_BUSY_CYCLES) relative to `{PROBE_KERNEL}`, the FMA probe; waits are shares of "
+             "SQ_WAVE_CYCLES.", "",
+             "| kernel | VALU instr per wave | VALU issue | SQ_WAIT_INST_ANY | SQ_WAIT_ANY |",
+             "|---|---|---|---|---|"]
+    fmt = lambda x, f: "-" if x is None else f.format(x)
+    for k in sorted(stats):
+        cs = stats[k]
+        per_wave = ratio(cs, "SQ_INSTS_VALU", "SQ_WAVES")
+        r = ratio(cs, "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES")
+        lines.append(f"| `{k}` | {fmt(per_wave, '{:.0f}')} | "
+                     f"{fmt(r / ref if r is not None and ref else None, '{:.1%}')} | "
+                     f"{fmt(ratio(cs, 'SQ_WAIT_INST_ANY', 'SQ_WAVE_CYCLES'), '{:.1%}')} | "
+                     f"{fmt(ratio(cs, 'SQ_WAIT_ANY', 'SQ_WAVE_CYCLES'), '{:.1%}')} |")
+    lines += ["", "Raw means per dispatch:", "",
+              "| kernel | " + " | ".join(counters) + " |", "|---|" + "---|" * len(counters)]
+    for k in sorted(stats):
+        lines.append(f"| `{k}` | " + " | ".join(fmt(stats[k].get(c), "{:.4g}") for c in counters) + " |")
+    return "\n".join(lines) + "\n"
+
+
 def trace_markdown(trace_csv: str, command: str, title: str, top: int = 14) -> str:
     """Per-(kernel, grid) statistics of a rocprofv3 --kernel-trace run
     (kernel_trace.csv), so launches of one kernel at different sizes (the
@@ -179,8 +240,15 @@ def main(argv=None):
     s.add_argument("--out", required=True)
     s.add_argument("--command", required=True)
     s.add_argument("--title", default="rocprofv3 kernel trace")
+    i = sub.add_parser("issue")
+    i.add_argument("--pmc", nargs="+", required=True, help="counter_collection.csv files or folders")
+    i.add_argument("--out", required=True)
+    i.add_argument("--command", required=True)
+    i.add_argument("--title", default="rocprofv3 SQ counters of the path's kernels")
     a = ap.parse_args(argv)
-    if a.cmd == "traffic":
+    if a.cmd == "issue":
+        text = issue_markdown(issue(a.pmc), a.command, a.title)
+    elif a.cmd == "traffic":
         tr = traffic(a.fetch, a.write, a.kernel)
         text = traffic_markdown(a.kernel.replace(" ", ""), tr, a.command, a.title)
     else:
