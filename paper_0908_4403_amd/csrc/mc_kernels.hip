@@ -4,9 +4,10 @@
 // reduction gives sigma and its error.  All FP64.
 //
 // Determinism: compaction keeps point order (block counts -> each block's
-// offset summed from its predecessors' counts -> in-block ballot ranks), and every sum is a fixed tree (64-point tiles by
-// xor shuffles, tiles in index order), so a configuration gives bitwise the
-// same sigma on every run.
+// offset summed from its predecessors' counts -> in-block ballot ranks), and
+// every sum is a fixed tree (64-point tiles by a fixed tree of cross-lane
+// moves, tiles in index order), so a configuration gives bitwise the same
+// sigma on every run.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
