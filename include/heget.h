@@ -168,6 +168,30 @@ typedef enum {
 heget_status heget_xsec_hist(int n, const heget_config *cfg, int observable, int nbins, double lo,
                              double hi, double *hist, heget_result *out);
 
+/* heget_xsec plus the record of every generated event, the per-event output
+ * of the paper's program (Section 3.1: the momenta and helicities of each
+ * event beside its weight).  For point i (0 <= i < npoints) of the same sample:
+ *   weight[i]   its weight w_i in fb (eq. (1)-(2)), so that sigma = sum_i
+ *               weight[i] / n_gen; 0 for points failing the cuts (or, in
+ *               HEGET_PP_TOY, below sqrt_shat_lo);
+ *   momenta     if not NULL, [npoints][n+2][4]: (E, px, py, pz) in GeV of u,
+ *               ubar and photons 1..n in the partonic CM frame (u along +z),
+ *               the layout of heget_gen_points;
+ *   rapidity    if not NULL, [npoints]: rapidity of the partonic CM frame in
+ *               the lab (0 unless HEGET_PP_TOY).  The weight covers both beam
+ *               assignments of eq. (1): the event boosted by +rapidity, and
+ *               its mirror (rotated by pi about x, boosted by -rapidity);
+ *   helicity    if not NULL (needs cfg->helicity_sampling = 1), [npoints]:
+ *               the configuration drawn for the point: bit 0 the quark pair
+ *               (0: h_u = -1, h_ubar = +1; 1: h_u = +1, h_ubar = -1), bit
+ *               1 + j photon j's helicity (1: +1).
+ * A HEGET_PP_TOY point below sqrt_shat_lo is no event: only its weight (0) is
+ * defined there, its momenta and rapidity are placeholders.  All arrays are
+ * host memory of the caller, written before the call returns; *out is as
+ * heget_xsec's. */
+heget_status heget_xsec_events(int n, const heget_config *cfg, heget_result *out, double *weight,
+                               double *momenta, double *rapidity, uint16_t *helicity);
+
 /* Several cross sections in one device pass (e.g. n = 2..7 with different
  * point counts), captured on first use as ONE hipGraph that later calls with
  * the same arguments replay.  Two schedules of the amplitude work:

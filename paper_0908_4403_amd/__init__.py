@@ -38,6 +38,7 @@ OBS_PT_MAX, OBS_DR_MIN = 0, 1
 
 EXPORTS = ["heget_gen_points", "heget_gen_points_device", "heget_me2", "heget_me2_device",
            "heget_xsec", "heget_xsec_async", "heget_xsec_device", "heget_xsec_hist",
+           "heget_xsec_events",
            "heget_xsec_batch",
            "heget_set_batch_schedule", "heget_batch_schedule_in_use",
            "heget_set_couplings",
@@ -405,6 +406,29 @@ def xsec_hist(n: int, cfg: Config, observable: int, nbins: int, lo: float, hi: f
     _check(_lib.heget_xsec_hist(n, C.byref(c), observable, nbins, lo, hi, _ptr(h), C.byref(r)),
            "heget_xsec_hist")
     return h, r.as_dict()
+
+
+def xsec_events(n: int, cfg: Config, momenta: bool = False, rapidity: bool = False,
+                helicity: bool = False) -> dict:
+    """heget_xsec plus per-event records: dict(result, weight[npoints] and, if
+    asked for, momenta[npoints, n+2, 4] (partonic CM frame), rapidity[npoints],
+    helicity[npoints] (uint16: bit 0 quark pair, bit 1 + j photon j is +1))."""
+    npts = max(int(cfg.npoints), 0)
+    out = {"weight": np.zeros(npts)}
+    if momenta:
+        out["momenta"] = np.zeros((npts, n + 2, 4))
+    if rapidity:
+        out["rapidity"] = np.zeros(npts)
+    if helicity:
+        out["helicity"] = np.zeros(npts, dtype=np.uint16)
+    r = Result()
+    c = cfg.c()
+    opt = lambda k: _ptr(out[k]) if k in out else None
+    hp = out["helicity"].ctypes.data_as(C.POINTER(C.c_uint16)) if helicity else None
+    _check(_lib.heget_xsec_events(n, C.byref(c), C.byref(r), _ptr(out["weight"]), opt("momenta"),
+                                  opt("rapidity"), hp), "heget_xsec_events")
+    out["result"] = r.as_dict()
+    return out
 
 
 # ---- the massless HELAS set (Appendix B) as a device library

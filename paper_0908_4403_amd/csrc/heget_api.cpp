@@ -87,7 +87,7 @@ constexpr int kRing = 256;
 
 enum Slot {
     S_MOM, S_WFAC, S_FLAG, S_BCOUNT, S_COUNT, S_INDEX, S_PART, S_PARTIALS, S_RES, S_FLAGS,
-    S_OUT, S_BATCH, S_HEL, S_WOUT, S_BINS, S_HIST, S_NSLOTS
+    S_OUT, S_BATCH, S_HEL, S_WOUT, S_BINS, S_HIST, S_EVW, S_EVY, S_EVH, S_NSLOTS
 };
 
 // Captured mixed-n batches, keyed by their configuration; replayed on repeat calls.
@@ -645,10 +645,18 @@ struct HistReq {
     double *host;  // [nbins + 2], written by a copy enqueued on the stream
 };
 
+// Per-event records to copy out beside the cross section (heget_xsec_events):
+// host arrays of npoints entries (momenta_soa: (n + 2) * 4 rows of npoints).
+struct EventReq {
+    double *weight, *momenta_soa, *rapidity;
+    uint16_t *helicity;
+};
+
 // Enqueue the whole path.  The result goes to d_out (device-writable, filled by
 // a kernel) when given, else to *out through the pinned ring and a host callback.
 heget_status xsec_enqueue(int n, const heget_config *cfg, heget_result *out, heget_result *d_out,
-                          hipStream_t s, unsigned **flags_out, const HistReq *hist = nullptr)
+                          hipStream_t s, unsigned **flags_out, const HistReq *hist = nullptr,
+                          const EventReq *ev = nullptr)
 {
     const int64_t np = cfg->npoints;
     const bool sampled = cfg->helicity_sampling != 0;
@@ -672,8 +680,15 @@ heget_status xsec_enqueue(int n, const heget_config *cfg, heget_result *out, heg
     b.wout = nullptr;
     unsigned long long *bins = nullptr;
     double *d_hist = nullptr;
+    if (hist || ev) HG_TRY(scratch_t<double>(S_WOUT, size_t(np), &b.wout));
+    double *ev_w = nullptr, *ev_y = nullptr;
+    uint16_t *ev_h = nullptr;
+    if (ev) {
+        HG_TRY(scratch_t<double>(S_EVW, size_t(np), &ev_w));
+        if (ev->rapidity) HG_TRY(scratch_t<double>(S_EVY, size_t(np), &ev_y));
+        if (ev->helicity) HG_TRY(scratch_t<uint16_t>(S_EVH, size_t(np), &ev_h));
+    }
     if (hist) {
-        HG_TRY(scratch_t<double>(S_WOUT, size_t(np), &b.wout));
         HG_TRY(scratch_t<unsigned long long>(S_BINS, size_t(hist->nbins) + 2, &bins));
         HG_TRY(scratch_t<double>(S_HIST, size_t(hist->nbins) + 2, &d_hist));
     }
@@ -693,6 +708,21 @@ heget_status xsec_enqueue(int n, const heget_config *cfg, heget_result *out, heg
         HG_HIP(heget::launch_hist_finish(bins, hist->nbins, b.res, np, d_hist, s));
         HG_HIP(hipMemcpyAsync(hist->host, d_hist, sizeof(double) * size_t(hist->nbins + 2),
                               hipMemcpyDeviceToHost, s));
+    }
+    if (ev) {
+        const heget::GenParams gp = slice_gen_params(n, *cfg);
+        HG_HIP(heget::launch_events(n, gp, ev_w, ev_y, ev_h, s));
+        HG_HIP(heget::launch_event_scatter(b.index, b.wout, b.d_count, np, ev_w, s));
+        HG_HIP(hipMemcpyAsync(ev->weight, ev_w, sizeof(double) * size_t(np), hipMemcpyDeviceToHost, s));
+        if (ev_y)
+            HG_HIP(hipMemcpyAsync(ev->rapidity, ev_y, sizeof(double) * size_t(np),
+                                  hipMemcpyDeviceToHost, s));
+        if (ev_h)
+            HG_HIP(hipMemcpyAsync(ev->helicity, ev_h, sizeof(uint16_t) * size_t(np),
+                                  hipMemcpyDeviceToHost, s));
+        if (ev->momenta_soa)
+            HG_HIP(hipMemcpyAsync(ev->momenta_soa, b.mom, sizeof(double) * size_t(n + 2) * 4 * size_t(np),
+                                  hipMemcpyDeviceToHost, s));
     }
     if (!d_out) {
         const unsigned slot = g.ring.fetch_add(1) % kRing;
@@ -1229,6 +1259,37 @@ heget_status heget_xsec_hist(int n, const heget_config *cfg, int observable, int
     unsigned flags = 0;
     HG_HIP(hipMemcpyAsync(&flags, d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, g.stream));
     HG_HIP(hipStreamSynchronize(g.stream));
+    return mc_flags_status(flags);
+}
+
+heget_status heget_xsec_events(int n, const heget_config *cfg, heget_result *out, double *weight,
+                               double *momenta, double *rapidity, uint16_t *helicity)
+{
+    g_err.clear();
+    HG_TRY(check_config(n, cfg));
+    if (!out || !weight) return fail(HEGET_ERR_ARG, "out and weight must not be NULL");
+    if (helicity && !cfg->helicity_sampling)
+        return fail(HEGET_ERR_ARG, "helicities are drawn only with helicity_sampling = 1");
+    const int64_t np = cfg->npoints;
+    if (np == 0) {
+        *out = heget_result{};
+        return HEGET_OK;
+    }
+    std::vector<double> soa;
+    if (momenta) soa.resize(size_t(n + 2) * 4 * size_t(np));
+    std::lock_guard<std::mutex> lk(g_mu);
+    HG_TRY(ensure_device());
+    unsigned *d_flags = nullptr;
+    const EventReq req{weight, momenta ? soa.data() : nullptr, rapidity, helicity};
+    HG_TRY(xsec_enqueue(n, cfg, out, nullptr, g.stream, &d_flags, nullptr, &req));
+    unsigned flags = 0;
+    HG_HIP(hipMemcpyAsync(&flags, d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, g.stream));
+    HG_HIP(hipStreamSynchronize(g.stream));
+    if (momenta) {
+        const size_t rows = size_t(n + 2) * 4;
+        for (int64_t i = 0; i < np; ++i)
+            for (size_t r = 0; r < rows; ++r) momenta[size_t(i) * rows + r] = soa[r * size_t(np) + size_t(i)];
+    }
     return mc_flags_status(flags);
 }
 

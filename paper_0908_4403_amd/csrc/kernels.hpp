@@ -90,6 +90,14 @@ hipError_t launch_gen(int n, const GenParams &g, double *mom, int64_t ld, double
 hipError_t launch_compact(const uint8_t *flag, int64_t np, const int32_t *counts, int32_t *index,
                           int64_t *d_count, hipStream_t stream);
 
+// Event records of a cross-section call, per generated point of g: w_all = 0,
+// y = rapidity of the partonic frame, hel = the raw helicity draw (each
+// optional but w_all); then w_all[index[k]] = w[k] for the survivors.
+hipError_t launch_events(int n, const GenParams &g, double *w_all, double *y, uint16_t *hel,
+                         hipStream_t stream);
+hipError_t launch_event_scatter(const int32_t *index, const double *w, const int64_t *d_count,
+                                int64_t max_count, double *w_all, hipStream_t stream);
+
 // Sum of helicity chunks: out[k] = sum_c part[c*ld + k]; with `partials`, the
 // per-tile weighted triples of sum_c part * wfac[index[k]] instead (as the
 // amplitude kernel's one-chunk epilogue).

@@ -234,21 +234,27 @@ struct GenParams {
 };
 
 // Helicity configuration drawn for `point` in sampling mode (the paper's
-// per-event helicities, Section 3.1): word 0 of the generator at block 0 of
-// stream 2.  Bit 0 picks the quark pair (0: h_u = -1, h_ubar = +1, the pair
-// the amplitude kernel evaluates; 1: its parity image), bit 1 + j the
-// helicity of photon j (1: +1).  Returned in the amplitude kernel's
-// convention: photon bits of the evaluated pair, flipped for the parity image
-// (|M(-h, -lam)| = |M(h, lam)|).
-template <int N>
-__device__ __forceinline__ uint16_t draw_helicity(uint64_t seed, uint64_t point)
+// per-event helicities, Section 3.1): the low n + 1 bits of word 0 of the
+// generator at block 0 of stream 2.  Bit 0 picks the quark pair (0: h_u = -1,
+// h_ubar = +1, the pair the amplitude kernel evaluates; 1: its parity image),
+// bit 1 + j the helicity of photon j (1: +1).
+__device__ __forceinline__ uint32_t draw_helicity_raw(uint64_t seed, uint64_t point, int n)
 {
     const Words4 r = philox4x32_10(static_cast<uint32_t>(point), static_cast<uint32_t>(point >> 32),
                                    0u, 2u, static_cast<uint32_t>(seed),
                                    static_cast<uint32_t>(seed >> 32));
+    return r.w0 & ((2u << n) - 1u);
+}
+
+// The same draw in the amplitude kernel's convention: photon bits of the
+// evaluated pair, flipped for the parity image (|M(-h, -lam)| = |M(h, lam)|).
+template <int N>
+__device__ __forceinline__ uint16_t draw_helicity(uint64_t seed, uint64_t point)
+{
+    const uint32_t raw = draw_helicity_raw(seed, point, N);
     const uint32_t mask = (1u << N) - 1u;
-    const uint32_t lam = (r.w0 >> 1) & mask;
-    return static_cast<uint16_t>((r.w0 & 1u) ? (~lam & mask) : lam);
+    const uint32_t lam = (raw >> 1) & mask;
+    return static_cast<uint16_t>((raw & 1u) ? (~lam & mask) : lam);
 }
 
 struct PointKin {

@@ -121,6 +121,37 @@ compact_kernel(const uint8_t *__restrict__ flag, int64_t np, const int32_t *__re
         *d_count = offset + wave_count[0] + wave_count[1] + wave_count[2] + wave_count[3];
 }
 
+// ---------------------------------------------------------------- event records
+
+// Per generated point of an events call: weight 0 (the survivors' weights
+// are scattered in afterwards), the rapidity of the partonic frame in the lab,
+// the helicity configuration drawn in sampling mode (bit layout of
+// draw_helicity_raw).
+template <int MODE>
+__global__ void __launch_bounds__(256)
+event_fill_kernel(GenParams g, int n, double *__restrict__ w_all, double *__restrict__ y_out,
+                  uint16_t *__restrict__ hel_out)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= g.npoints) return;
+    const uint64_t point = static_cast<uint64_t>(g.first + i);
+    w_all[i] = 0.0;
+    if (y_out) y_out[i] = point_kinematics<MODE>(g, point).y;
+    if (hel_out) hel_out[i] = static_cast<uint16_t>(draw_helicity_raw(g.seed, point, n));
+}
+
+// Survivor weights back to point order: w_all[index[k]] = w[k], k < *d_count.
+__global__ void __launch_bounds__(256)
+event_scatter_kernel(const int32_t *__restrict__ index, const double *__restrict__ w,
+                     const int64_t *__restrict__ d_count, int64_t max_count,
+                     double *__restrict__ w_all)
+{
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t count = *d_count;
+    if (k >= count || k >= max_count) return;
+    w_all[index[k]] = w[k];
+}
+
 // ---------------------------------------------------------------- sums
 
 __global__ void __launch_bounds__(256)
@@ -355,6 +386,28 @@ hipError_t launch_gen(int n, const GenParams &g, double *mom, int64_t ld, double
     case 8: return gen_n<8>(g, mom, ld, w, flag, block_count, stream);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_events(int n, const GenParams &g, double *w_all, double *y, uint16_t *hel,
+                         hipStream_t stream)
+{
+    const int64_t blocks = (g.npoints + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    const auto kern = g.mode == 1 ? event_fill_kernel<1> : g.mode == 2 ? event_fill_kernel<2>
+                                                                         : event_fill_kernel<0>;
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, g, n, w_all,
+                       y, hel);
+    return hipGetLastError();
+}
+
+hipError_t launch_event_scatter(const int32_t *index, const double *w, const int64_t *d_count,
+                                int64_t max_count, double *w_all, hipStream_t stream)
+{
+    const int64_t blocks = (max_count + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(event_scatter_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                       stream, index, w, d_count, max_count, w_all);
+    return hipGetLastError();
 }
 
 hipError_t launch_compact(const uint8_t *flag, int64_t np, const int32_t *counts, int32_t *index,

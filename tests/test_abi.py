@@ -75,6 +75,11 @@ def test_argument_checks_run_on_the_host():
         assert e.value.status == status, args
     h, r = H.xsec_hist(4, H.Config(npoints=0), H.OBS_PT_MAX, 8, 0.0, 100.0)
     assert r["n_gen"] == 0 and not h.any()
+    with pytest.raises(H.HegetError) as e:  # helicities exist only when they are drawn
+        H.xsec_events(4, H.Config(npoints=16), helicity=True)
+    assert e.value.status == H.ERR_ARG
+    ev = H.xsec_events(4, H.Config(npoints=0), momenta=True, rapidity=True)
+    assert ev["result"]["n_gen"] == 0 and ev["momenta"].shape == (0, 6, 4)
     with pytest.raises(H.HegetError):
         H.gen_points(3, float("inf"))
     with pytest.raises(H.HegetError):

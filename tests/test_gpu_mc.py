@@ -232,3 +232,66 @@ def test_histogram_matches_oracle_same_sample(H, orc, n, which, lo, hi, sampling
         big = ref > 1e-3 * ref.max()
         assert np.all(np.abs(got[big] / ref[big] - 1) < tol_bin), (prec, got, ref)
         assert np.all((got > 0) == (ref > 0))
+
+
+def _helicity_bits(orc, n, seed, i):
+    h1, _, lam = orc.draw_helicity(n, seed, i)
+    bits = 1 if h1 == 1 else 0
+    for j, l in enumerate(lam):
+        bits |= (1 << (1 + j)) if l == 1 else 0
+    return bits
+
+
+@pytest.mark.parametrize("n,mode,extra,npoints,sampling", [
+    (3, "FIXED_SHAT", dict(sqrt_s=1000.0), 3000, 0),
+    (2, "PP_TOY", dict(sqrt_s=14000.0, sqrt_shat_lo=150.0), 4100, 0),
+    (4, "UNIFORM_SQRTSHAT", dict(sqrt_shat_lo=200.0, sqrt_shat_hi=2000.0), 1500, 1),
+])
+def test_event_records_match_oracle(H, orc, n, mode, extra, npoints, sampling):
+    """heget_xsec_events: every generated point's weight, momenta, frame
+    rapidity and drawn helicities against the oracle's own events."""
+    kw = dict(seed=8, npoints=npoints, pt_min=20.0, eta_max=2.5, dr_min=0.4, **extra)
+    hc, oc = _cfgs(H, orc, getattr(H, mode), prec=H.FP64, helicity_sampling=sampling, **kw)
+    ev = H.xsec_events(n, hc, momenta=True, rapidity=True, helicity=bool(sampling))
+    want = orc.xsec(n, oc, want_weights=True)
+    r = ev["result"]
+    assert r == H.xsec(n, hc)  # the same pass as heget_xsec
+    assert r["n_acc"] == want["n_acc"]
+    w, wo = ev["weight"], want["w"]
+    # survivors and the scale of their weights: the helicity-summed weight
+    # (with sampling, the drawn configuration may be one whose amplitude
+    # vanishes, where both sides hold rounding noise of that scale)
+    _, oc_sum = _cfgs(H, orc, getattr(H, mode), prec=H.FP64, **kw)
+    scale = orc.xsec(n, oc_sum, want_weights=True)["w"] if sampling else wo
+    surv = scale != 0
+    assert int(surv.sum()) == r["n_acc"] and not w[~surv].any()
+    # each side generates the momenta itself (they agree to 1e-12 of sqrt(shat),
+    # nearly collinear n = 2 seeds amplifying the rounding of the generation):
+    # the weights follow within 1e-11 of their scale, most of them to a few ulp
+    err = np.abs(w[surv] - wo[surv]) / scale[surv]
+    assert err.max() <= 1e-11 and np.median(err) <= 1e-14
+    assert abs(w.sum() / r["n_gen"] / r["sigma_fb"] - 1) <= 1e-12
+    checked = 0
+    for i in range(0, npoints, 37):
+        acc, p, y, _, _ = orc.point(n, oc, i)
+        e_cm = p[0, 0] + p[1, 0]
+        if mode == "PP_TOY" and e_cm < extra["sqrt_shat_lo"]:
+            continue  # below threshold: no event, only the weight 0 is defined
+        checked += 1
+        assert np.abs(ev["momenta"][i] - p).max() <= 1e-12 * e_cm, i
+        assert abs(ev["rapidity"][i] - y) <= 1e-12, i
+        if sampling:
+            assert int(ev["helicity"][i]) == _helicity_bits(orc, n, 8, i), i
+    assert checked >= npoints // 37 // 2
+    if mode != "PP_TOY":
+        assert not ev["rapidity"].any()
+
+
+def test_event_records_fp32_weights(H, orc):
+    kw = dict(seed=9, npoints=2000, sqrt_s=1000.0, pt_min=20.0, eta_max=2.5, dr_min=0.4)
+    hc, oc = _cfgs(H, orc, H.FIXED_SHAT, prec=H.FP32, **kw)
+    w = H.xsec_events(4, hc)["weight"]
+    wo = orc.xsec(4, oc, want_weights=True)["w"]
+    assert np.array_equal(w == 0, wo == 0)
+    rel = np.abs(w[wo != 0] / wo[wo != 0] - 1)
+    assert np.median(rel) <= 1e-5 and np.quantile(rel, 0.999) <= 1e-3
