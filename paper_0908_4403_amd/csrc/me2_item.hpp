@@ -91,18 +91,23 @@ __device__ __forceinline__ void me2_compute(const PointLoad<N> &q, int64_t npts,
         const double pt2 = kx * kx + ky * ky;
         ok = ok && E > 0.0 && pt2 > 0.0;
         // k+ k- = pT^2 for a massless photon: the light-cone component free of
-        // cancellation is E + |kz|, the other one pT^2 / (E + |kz|)
+        // cancellation is E + |kz|, the other one pT^2 / (E + |kz|) (for FP32
+        // amplitudes through the hardware reciprocal: within an FP32 ulp or so)
         const double big = E + fabs(kz);
-        const double small = pt2 / big;
-        const double kp = kz >= 0.0 ? big : small;
-        const double km = kz >= 0.0 ? small : big;
+        R small;
+        if constexpr (std::is_same<R, float>::value)
+            small = static_cast<float>(pt2) * __builtin_amdgcn_rcpf(static_cast<float>(big));
+        else
+            small = pt2 / big;
+        const R kp = kz >= 0.0 ? static_cast<R>(big) : small;
+        const R km = kz >= 0.0 ? small : static_cast<R>(big);
         // vertex normalisation t ~ 1/(sqrt(2) E pT), any rounding of it: the
         // remainder (1/(sqrt(2) E pT t))^2 goes into the FP64 normalisation
         const double e2pt2 = 2.0 * E * E * pt2;
         const R t = rsqrt_approx(static_cast<R>(e2pt2));
         const double td = static_cast<double>(t);
         norm_den *= e2pt2 * td * td;
-        in.k[j] = {static_cast<R>(kp), static_cast<R>(km), static_cast<R>(kx), static_cast<R>(ky), t};
+        in.k[j] = {kp, km, static_cast<R>(kx), static_cast<R>(ky), t};
         if constexpr (kTopInLds) {
             tab[0 * N * 64 + j * 64 + lane] = in.k[j].p;
             tab[1 * N * 64 + j * 64 + lane] = in.k[j].m;
