@@ -28,18 +28,19 @@ struct PointLoad {
 };
 
 // Column of mom holding lane `lane` of `tile`: past the last point the tile
-// repeats the last point (its result is not stored).
-__device__ __forceinline__ int64_t point_column(const int32_t *__restrict__ index, int64_t npts,
-                                                int64_t tile, int lane)
+// repeats the last point (its result is not stored).  Columns are below 2^31;
+// kept unsigned so that widening one needs no wait for the load that gave it.
+__device__ __forceinline__ uint32_t point_column(const int32_t *__restrict__ index, int64_t npts,
+                                                 int64_t tile, int lane)
 {
     const int64_t i = tile * 64 + lane;
     const int64_t ic = i < npts ? i : npts - 1;
-    return index ? static_cast<int64_t>(index[ic]) : ic;
+    return index ? static_cast<uint32_t>(index[ic]) : static_cast<uint32_t>(ic);
 }
 
 template <int N>
 __device__ __forceinline__ PointLoad<N> load_point(const double *__restrict__ mom, int64_t ld,
-                                                   int64_t src, const double *__restrict__ wfac,
+                                                   uint32_t src, const double *__restrict__ wfac,
                                                    const uint16_t *__restrict__ hel)
 {
     PointLoad<N> q;
@@ -149,7 +150,7 @@ __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t
                                          double *__restrict__ partials, double *__restrict__ wout,
                                          unsigned *__restrict__ flags, R *tab, int lane)
 {
-    const int64_t src = point_column(index, npts, tile, lane);
+    const uint32_t src = point_column(index, npts, tile, lane);
     const double *wf = kWeighted && partials && nchunks == 1 ? wfac : nullptr;
     const PointLoad<N> q = load_point<N>(mom, ld, src, wf, H == 0 ? hel : nullptr);
     me2_compute<R, N, MB, H, CL, kWeighted>(q, npts, tile, chunk, nchunks, coef, out, ld_out,
@@ -161,8 +162,8 @@ __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t
 // with PF = 1 it holds only the waves resident on the device and each wave
 // walks its items in turn, loading the next item's inputs (and the survivor
 // index of the one after) before the walk of the current one, so the walk
-// hides the memory latency even at one wave per SIMD.  The loop bounds are
-// the same on every lane of a wave.
+// hides the memory latency even at one wave per SIMD.  Item numbers are
+// wave-uniform (scalar registers), so the loop and its bounds are scalar.
 template <typename R, int N, int MB, int H, int CL, int WPB, int PF>
 __global__ void __launch_bounds__(WPB * 64)
 me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict__ index,
@@ -173,7 +174,7 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
 {
     __shared__ R tab_all[N > MB ? WPB * kPhotonFields * N * 64 : 1];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t npts = d_count ? *d_count : count;
     const int64_t nitems = ((npts + 63) >> 6) * nchunks;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WPB;
@@ -182,32 +183,35 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
     R *tab = tab_all + (N > MB ? wave * kPhotonFields * N * 64 : 0);
     const double *wf = partials && nchunks == 1 ? wfac : nullptr;
     const uint16_t *hl = H == 0 ? hel : nullptr;
+    auto tile_of = [nchunks](int64_t it) -> int64_t { return nchunks == 1 ? it : it / nchunks; };
     if constexpr (PF == 0) {
         for (; item < nitems; item += stride) {
-            const int64_t tile = item / nchunks;
+            const int64_t tile = tile_of(item);
             const int chunk = static_cast<int>(item - tile * nchunks);
             const PointLoad<N> q = load_point<N>(mom, ld, point_column(index, npts, tile, lane), wf, hl);
             me2_compute<R, N, MB, H, CL>(q, npts, tile, chunk, nchunks, coef, out, ld_out, partials,
                                          wout, flags, tab, lane);
         }
     } else {
-        PointLoad<N> cur = load_point<N>(mom, ld, point_column(index, npts, item / nchunks, lane), wf, hl);
-        int64_t next = item + stride;
-        int64_t src_next = next < nitems ? point_column(index, npts, next / nchunks, lane) : 0;
+        // Loads for items past the last one read the last tile again (their
+        // values are never used): every load is unconditional, so none has to
+        // complete at a branch join before the walk it was issued ahead of.
+        const int64_t last_tile = (npts - 1) >> 6;
+        auto ahead = [&](int64_t it) -> int64_t {
+            const int64_t t = tile_of(it);
+            return t < last_tile ? t : last_tile;
+        };
+        PointLoad<N> cur = load_point<N>(mom, ld, point_column(index, npts, tile_of(item), lane), wf, hl);
+        uint32_t src_next = point_column(index, npts, ahead(item + stride), lane);
         for (;;) {
-            PointLoad<N> nxt;
-            int64_t src_after = 0;
-            if (next < nitems) {
-                nxt = load_point<N>(mom, ld, src_next, wf, hl);
-                if (next + stride < nitems) src_after = point_column(index, npts, (next + stride) / nchunks, lane);
-            }
-            const int64_t tile = item / nchunks;
+            const PointLoad<N> nxt = load_point<N>(mom, ld, src_next, wf, hl);
+            const uint32_t src_after = point_column(index, npts, ahead(item + 2 * stride), lane);
+            const int64_t tile = tile_of(item);
             const int chunk = static_cast<int>(item - tile * nchunks);
             me2_compute<R, N, MB, H, CL>(cur, npts, tile, chunk, nchunks, coef, out, ld_out, partials,
                                          wout, flags, tab, lane);
-            if (next >= nitems) break;
-            item = next;
-            next += stride;
+            item += stride;
+            if (item >= nitems) break;
             cur = nxt;
             src_next = src_after;
         }
