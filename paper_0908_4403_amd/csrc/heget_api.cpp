@@ -12,6 +12,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <exception>
 #include <vector>
 
 #include "heget.h"
@@ -32,6 +33,18 @@ heget_status fail(heget_status s, const std::string &msg)
 {
     g_err = msg;
     return s;
+}
+
+// Host staging of `count` doubles; an allocation failure becomes
+// HEGET_ERR_ALLOC instead of an exception crossing the C ABI.
+heget_status host_buffer(std::vector<double> &v, size_t count)
+{
+    try {
+        v.resize(count);
+    } catch (const std::exception &) {
+        return fail(HEGET_ERR_ALLOC, "host staging buffer: out of memory");
+    }
+    return HEGET_OK;
 }
 
 #define HG_HIP(expr)                                                                          \
@@ -975,7 +988,8 @@ heget_status heget_gen_points(int n, double sqrt_s, const heget_cuts *cuts, uint
     gp.partonic_coef = partonic_coef(n);
     gp.weight_kind = 0;
     HG_HIP(heget::launch_gen(n, gp, d_mom, npoints, d_w, nullptr, nullptr, s));
-    std::vector<double> soa(rows * size_t(npoints));
+    std::vector<double> soa;
+    HG_TRY(host_buffer(soa, rows * size_t(npoints)));
     HG_HIP(hipMemcpyAsync(soa.data(), d_mom, soa.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HG_HIP(hipMemcpyAsync(weight, d_w, size_t(npoints) * sizeof(double), hipMemcpyDeviceToHost, s));
     HG_HIP(hipStreamSynchronize(s));
@@ -1027,7 +1041,8 @@ heget_status heget_me2(int n, int64_t npoints, const double *momenta, double *ou
     std::lock_guard<std::mutex> lk(g_mu);
     HG_TRY(ensure_device());
     const size_t rows = size_t(n + 2) * 4;
-    std::vector<double> soa(rows * size_t(npoints));
+    std::vector<double> soa;
+    HG_TRY(host_buffer(soa, rows * size_t(npoints)));
     for (int64_t i = 0; i < npoints; ++i)
         for (size_t r = 0; r < rows; ++r) soa[r * size_t(npoints) + size_t(i)] = momenta[size_t(i) * rows + r];
     double *d_mom, *d_out;
@@ -1163,7 +1178,8 @@ heget_status heget_me2_frame(int n, int64_t npoints, const double *momenta, doub
     std::lock_guard<std::mutex> lk(g_mu);
     HG_TRY(ensure_device());
     const size_t rows = size_t(n + 2) * 4;
-    std::vector<double> soa(rows * size_t(npoints));
+    std::vector<double> soa;
+    HG_TRY(host_buffer(soa, rows * size_t(npoints)));
     for (int64_t i = 0; i < npoints; ++i)
         for (size_t r = 0; r < rows; ++r) soa[r * size_t(npoints) + size_t(i)] = momenta[size_t(i) * rows + r];
     double *d_mom, *d_out;
@@ -1276,7 +1292,7 @@ heget_status heget_xsec_events(int n, const heget_config *cfg, heget_result *out
         return HEGET_OK;
     }
     std::vector<double> soa;
-    if (momenta) soa.resize(size_t(n + 2) * 4 * size_t(np));
+    if (momenta) HG_TRY(host_buffer(soa, size_t(n + 2) * 4 * size_t(np)));
     std::lock_guard<std::mutex> lk(g_mu);
     HG_TRY(ensure_device());
     unsigned *d_flags = nullptr;
