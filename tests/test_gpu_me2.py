@@ -149,3 +149,26 @@ def test_autotune_picks_a_compiled_shape(H, orc, tmp_path, monkeypatch):
     ref, _ = orc.me2_batch(ev)
     assert np.median(np.abs(H.me2(ev, H.FP32) / ref - 1)) <= 1e-5
     H.set_kernel_shape(5, H.FP32)
+
+
+def test_resident_loop_many_items_and_chunks(H, orc):
+    """The prefetching resident-wave kernels over several work items per wave
+    with the helicity walks split into chunks (20000 points at n = 5: 313
+    tiles x 16 chunks, about five items per wave), against the oracle on every
+    tenth point."""
+    n = 5
+    ev = cut_events(orc, n, 1000.0, 31, 20000)
+    ref, _ = orc.me2_batch(ev[::10])
+    try:
+        for prec, shape in ((H.FP64, (4, 2, 3, 1, 1)), (H.FP32, (5, 2, 3, 1, 1))):
+            H.set_kernel_shape(n, prec, shape)
+            rel = np.abs(H.me2(ev, prec)[::10] / ref - 1.0)
+            print(f"n={n} prec={prec} shape={shape} max rel {rel.max():.2e} median {np.median(rel):.2e}",
+                  flush=True)
+            if prec == H.FP64:
+                assert rel.max() <= 1e-12
+            else:
+                assert np.median(rel) <= 1e-5 and np.quantile(rel, 0.999) <= 1e-3
+    finally:
+        H.set_kernel_shape(n, H.FP64)
+        H.set_kernel_shape(n, H.FP32)
