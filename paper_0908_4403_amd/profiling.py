@@ -53,7 +53,7 @@ def source_digest() -> str:
 
 def short_name(kernel: str) -> str:
     """'void heget::me2_kernel<float, 4, 4, 16, 2, 1>(double const*, ...)' -> 'me2_kernel<float,4,4,16,2,1>'."""
-    k = kernel.split("(")[0].replace("void ", "").replace(" ", "")
+    k = kernel.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").replace(" ", "")
     return k[len("heget::"):] if k.startswith("heget::") else k
 
 
@@ -114,7 +114,7 @@ def traffic_markdown(kernel: str, t: dict, command: str, title: str) -> str:
     return "\n".join([
         f"# {title}",
         "",
-        "Commands (GPU box, from the repository root):",
+        "Commands (on the MI355X host, from the repository root):",
         "",
         "    " + command,
         "",
@@ -181,7 +181,7 @@ def issue_markdown(stats: dict, command: str, title: str) -> str:
         return cs[a] / cs[b] if a in cs and cs.get(b) else None
 
     ref = ratio(probe, "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES")
-    lines = [f"# {title}", "", "Commands (GPU box, from the repository root):", "", "    " + command, "",
+    lines = [f"# {title}", "", "Commands (on the MI355X host, from the repository root):", "", "    " + command, "",
              "Mean per dispatch (largest launch of each kernel). VALU issue = (SQ_ACTIVE_INST_VALU / "
              f"SQ_BUSY_CYCLES) relative to `{PROBE_KERNEL}`, the FMA probe; waits are shares of "
              "SQ_WAVE_CYCLES.", "",
@@ -215,7 +215,7 @@ def trace_markdown(trace_csv: str, command: str, title: str, top: int = 14) -> s
             groups.setdefault((short_name(r["Kernel_Name"]), grid), []).append(dur)
     total = sum(sum(v) for v in groups.values()) or 1.0
     rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))
-    lines = [f"# {title}", "", "Command (GPU box, from the repository root):", "", "    " + command, "",
+    lines = [f"# {title}", "", "Command (on the MI355X host, from the repository root):", "", "    " + command, "",
              "Durations in microseconds, per kernel and launch size (grid = threads).", "",
              "| kernel | grid | calls | total us | average us | min us | max us | % |",
              "|---|---|---|---|---|---|---|---|"]
