@@ -177,9 +177,24 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t npts = d_count ? *d_count : count;
     const int64_t nitems = ((npts + 63) >> 6) * nchunks;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * WPB;
+    int64_t stride = static_cast<int64_t>(gridDim.x) * WPB;
     int64_t item = static_cast<int64_t>(blockIdx.x) * WPB + wave;
-    if (item >= nitems) return;  // whole wave
+    int64_t end = nitems;
+    if constexpr (PF == 1) {
+        // Blocks go round-robin to the eight XCDs, each with its own L2.  With
+        // a grid of whole rounds, each XCD takes one contiguous range of
+        // items, so neighbouring tiles, which share cache lines of the
+        // gathered momenta, are read through one L2.
+        constexpr unsigned kXcds = 8;
+        if (gridDim.x % kXcds == 0) {
+            const int64_t x = blockIdx.x % kXcds;
+            const int64_t per = (nitems + kXcds - 1) / kXcds;
+            stride = static_cast<int64_t>(gridDim.x / kXcds) * WPB;
+            item = x * per + static_cast<int64_t>(blockIdx.x / kXcds) * WPB + wave;
+            end = (x + 1) * per < nitems ? (x + 1) * per : nitems;
+        }
+    }
+    if (item >= end) return;  // whole wave
     R *tab = tab_all + (N > MB ? wave * kPhotonFields * N * 64 : 0);
     const double *wf = partials && nchunks == 1 ? wfac : nullptr;
     const uint16_t *hl = H == 0 ? hel : nullptr;
@@ -211,7 +226,7 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
             me2_compute<R, N, MB, H, CL>(cur, npts, tile, chunk, nchunks, coef, out, ld_out, partials,
                                          wout, flags, tab, lane);
             item += stride;
-            if (item >= nitems) break;
+            if (item >= end) break;
             cur = nxt;
             src_next = src_after;
         }
