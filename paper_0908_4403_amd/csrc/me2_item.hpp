@@ -180,18 +180,24 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
     int64_t stride = static_cast<int64_t>(gridDim.x) * WPB;
     int64_t item = static_cast<int64_t>(blockIdx.x) * WPB + wave;
     int64_t end = nitems;
-    if constexpr (PF == 1) {
-        // Blocks go round-robin to the eight XCDs, each with its own L2.  With
-        // a grid of whole rounds, each XCD takes one contiguous range of
-        // items, so neighbouring tiles, which share cache lines of the
-        // gathered momenta, are read through one L2.
-        constexpr unsigned kXcds = 8;
-        if (gridDim.x % kXcds == 0) {
-            const int64_t x = blockIdx.x % kXcds;
+    // Blocks go round-robin to the eight XCDs, each with its own L2.  With a
+    // grid of whole rounds, each XCD takes one contiguous range of items, so
+    // neighbouring tiles, which share cache lines of the gathered momenta,
+    // are read through one L2.
+    constexpr unsigned kXcds = 8;
+    if (gridDim.x % kXcds == 0) {
+        const int64_t x = blockIdx.x % kXcds;
+        const int64_t rank = static_cast<int64_t>(blockIdx.x / kXcds) * WPB + wave;
+        if constexpr (PF == 1) {
+            // resident waves: XCD x walks items [x per, (x + 1) per)
             const int64_t per = (nitems + kXcds - 1) / kXcds;
             stride = static_cast<int64_t>(gridDim.x / kXcds) * WPB;
-            item = x * per + static_cast<int64_t>(blockIdx.x / kXcds) * WPB + wave;
+            item = x * per + rank;
             end = (x + 1) * per < nitems ? (x + 1) * per : nitems;
+        } else {
+            // one wave per item: the block order is permuted so that XCD x
+            // holds blocks x G/8 .. (x + 1) G/8 - 1 of each round of G
+            item = x * (static_cast<int64_t>(gridDim.x / kXcds) * WPB) + rank;
         }
     }
     if (item >= end) return;  // whole wave
