@@ -181,24 +181,17 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
     int64_t item = static_cast<int64_t>(blockIdx.x) * WPB + wave;
     int64_t end = nitems;
     // Blocks go round-robin to the eight XCDs, each with its own L2.  With a
-    // grid of whole rounds, each XCD takes one contiguous range of items, so
+    // grid of whole rounds, XCD x walks the contiguous items [x per,
+    // (x + 1) per) of the items that exist (the device-side count), so
     // neighbouring tiles, which share cache lines of the gathered momenta,
-    // are read through one L2.
+    // are read through one L2, and every XCD gets an equal share.
     constexpr unsigned kXcds = 8;
     if (gridDim.x % kXcds == 0) {
         const int64_t x = blockIdx.x % kXcds;
-        const int64_t rank = static_cast<int64_t>(blockIdx.x / kXcds) * WPB + wave;
-        if constexpr (PF == 1) {
-            // resident waves: XCD x walks items [x per, (x + 1) per)
-            const int64_t per = (nitems + kXcds - 1) / kXcds;
-            stride = static_cast<int64_t>(gridDim.x / kXcds) * WPB;
-            item = x * per + rank;
-            end = (x + 1) * per < nitems ? (x + 1) * per : nitems;
-        } else {
-            // one wave per item: the block order is permuted so that XCD x
-            // holds blocks x G/8 .. (x + 1) G/8 - 1 of each round of G
-            item = x * (static_cast<int64_t>(gridDim.x / kXcds) * WPB) + rank;
-        }
+        const int64_t per = (nitems + kXcds - 1) / kXcds;
+        stride = static_cast<int64_t>(gridDim.x / kXcds) * WPB;
+        item = x * per + static_cast<int64_t>(blockIdx.x / kXcds) * WPB + wave;
+        end = (x + 1) * per < nitems ? (x + 1) * per : nitems;
     }
     if (item >= end) return;  // whole wave
     R *tab = tab_all + (N > MB ? wave * kPhotonFields * N * 64 : 0);
@@ -206,7 +199,7 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
     const uint16_t *hl = H == 0 ? hel : nullptr;
     auto tile_of = [nchunks](int64_t it) -> int64_t { return nchunks == 1 ? it : it / nchunks; };
     if constexpr (PF == 0) {
-        for (; item < nitems; item += stride) {
+        for (; item < end; item += stride) {
             const int64_t tile = tile_of(item);
             const int chunk = static_cast<int>(item - tile * nchunks);
             const PointLoad<N> q = load_point<N>(mom, ld, point_column(index, npts, tile, lane), wf, hl);
