@@ -55,3 +55,37 @@ def test_read_traffic_checks_kernel_and_sources(tmp_path):
     md.write_text(md.read_text().replace(P.source_digest(), "0" * 16))
     assert P.read_traffic(str(md), k) is None
     assert P.read_traffic(str(tmp_path / "missing.md"), k) is None
+
+
+def test_short_name_of_anonymous_namespace_kernels():
+    name = "void heget::(anonymous namespace)::me2_frame_kernel<float, 5>(double const*, long)"
+    assert P.short_name(name) == "me2_frame_kernel<float,5>"
+
+
+def test_issue_summary_relates_valu_issue_to_the_probe(tmp_path):
+    """Counters of two passes average per dispatch (largest launch only) and
+    the VALU issue of a kernel is read relative to the FMA probe's."""
+    probe = "void heget::fma_peak_kernel<float>(float*, float, float, int)"
+    rows = [  # pass A
+        (probe, 1 << 20, "SQ_ACTIVE_INST_VALU", 800.0), (probe, 1 << 20, "SQ_BUSY_CYCLES", 100.0),
+        (KERNEL, 1 << 20, "SQ_ACTIVE_INST_VALU", 600.0), (KERNEL, 1 << 20, "SQ_BUSY_CYCLES", 100.0),
+        (KERNEL, 1 << 20, "SQ_INSTS_VALU", 4000.0), (KERNEL, 1 << 20, "SQ_WAVES", 10.0),
+        (KERNEL, 1 << 20, "SQ_WAVE_CYCLES", 1000.0), (KERNEL, 1 << 20, "SQ_WAIT_INST_ANY", 50.0),
+        (KERNEL, 1 << 18, "SQ_INSTS_VALU", 1.0),  # a smaller launch: ignored
+        (CALIB, 1 << 24, "SQ_WAVES", 5.0),         # not a kernel of the path: ignored
+    ]
+    for name, data in (("a", rows), ("b", [(KERNEL, 1 << 20, "SQ_WAIT_ANY", 120.0),
+                                           (KERNEL, 1 << 20, "SQ_WAVE_CYCLES", 1000.0)])):
+        os.makedirs(tmp_path / name)
+        with open(tmp_path / name / "run_counter_collection.csv", "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=FIELDS)
+            w.writeheader()
+            for i, (k, g, c, v) in enumerate(data):
+                w.writerow(dict(Dispatch_Id=i, Kernel_Name=k, Grid_Size=g, Counter_Name=c, Counter_Value=v))
+    st = P.issue([str(tmp_path / "a"), str(tmp_path / "b")])
+    assert set(st) == {"fma_peak_kernel<float>", "me2_kernel<float,4,4,16,2,1>"}
+    k = st["me2_kernel<float,4,4,16,2,1>"]
+    assert k["SQ_INSTS_VALU"] == 4000.0 and k["SQ_WAIT_ANY"] == 120.0
+    md = P.issue_markdown(st, "cmd", "title")
+    row = next(l for l in md.splitlines() if l.startswith("| `me2_kernel"))
+    assert "| 400 | 75.0% | 5.0% | 12.0% |" in row  # 4000/10 per wave, (600/100)/(800/100)
