@@ -437,3 +437,86 @@ def test_histogram_entries_add_up_to_sigma(orc, which, lo, hi):
     assert h.sum() == pytest.approx(s["sigma_fb"], rel=1e-13)
     assert h[0] == 0.0  # the cuts put every accepted point above lo
     assert (h >= 0).all() and (h[1:-1] > 0).sum() >= 10
+
+
+def _n2_observable(k, which):
+    """Leading pT (which = 0) or Delta R of the photon pair (1), computed here."""
+    if which == 0:
+        return np.max(np.hypot(k[..., 1], k[..., 2]), axis=1)
+    eta = np.arctanh(k[..., 3] / np.linalg.norm(k[..., 1:], axis=-1))
+    phi = np.arctan2(k[..., 2], k[..., 1])
+    dphi = np.abs(phi[:, 0] - phi[:, 1])
+    dphi = np.minimum(dphi, 2.0 * math.pi - dphi)
+    return np.hypot(eta[:, 0] - eta[:, 1], dphi)
+
+
+@pytest.mark.parametrize("which,lo,hi", [(0, 0.0, 256.0), (1, 3.0, 6.2)])
+def test_histogram_bins_against_the_n2_closed_form(orc, which, lo, hi):
+    """Fig. 2 distributions at n = 2, sqrt(shat) = 500 GeV, pT > 20, |eta| < 2.5.
+    The photons are back to back, so pT_max = (sqrt(shat)/2) sin(theta*) and
+    Delta R = sqrt((2 eta*)^2 + pi^2) are both monotone in |cos theta*|: the
+    expected content of a bin is sigma_hat(|cos| < c1) - sigma_hat(|cos| < c0)
+    of the closed form at the bin's two edges.  Each bin of the oracle must
+    agree within 4.5 of its own Monte-Carlo standard errors, and equal the
+    oracle's weights binned here by the observable computed here."""
+    sqrt_s, N, nb, seed = 500.0, 1 << 17, 8, 11
+    cfg = orc.Config(mode=0, seed=seed, npoints=N, sqrt_s=sqrt_s, pt_min=20.0, eta_max=2.5,
+                     dr_min=0.0)
+    h = orc.hist(2, cfg, which, nb, lo, hi)
+    w = orc.xsec(2, cfg, want_weights=True)["w"]
+    x = _n2_observable(orc.cm_events(2, sqrt_s, seed, 0, N)[:, 2:], which)
+    edges = lo + (hi - lo) * np.arange(nb + 1) / nb
+    idx = np.digitize(x, edges)  # 0 below lo, nb + 1 at or above hi
+    by_hand = np.array([w[idx == b].sum() for b in range(nb + 2)]) / N
+    assert np.allclose(h, by_hand, rtol=1e-12, atol=1e-15 * h.sum())
+
+    c_cut = pins.cos_max_n2(sqrt_s, 0.0, 20.0, 2.5)
+
+    def cos_at(v):  # |cos theta*| where the observable equals v
+        if which == 0:
+            s = 2.0 * v / sqrt_s
+            return math.sqrt(1.0 - s * s) if s < 1.0 else 0.0
+        return math.tanh(math.sqrt(max(v * v - math.pi ** 2, 0.0)) / 2.0)
+
+    def s_hat(c):
+        return pins.sigma_hat_n2(sqrt_s ** 2, ALPHA, Q, min(c, c_cut))
+
+    want = np.zeros(nb + 2)
+    for b in range(nb):
+        c0, c1 = cos_at(edges[b]), cos_at(edges[b + 1])
+        want[b + 1] = abs(s_hat(c1) - s_hat(c0))
+    assert want.sum() == pytest.approx(s_hat(1.0), rel=1e-12)  # every accepted point is in range
+    se = np.sqrt(np.maximum([np.sum(w[idx == b] ** 2) / N - h[b] ** 2 for b in range(nb + 2)], 0.0)
+                 / (N - 1))
+    filled = want > 0
+    assert filled.sum() >= 6
+    assert np.all(se[filled] < 0.1 * want[filled])  # the comparison has power
+    assert np.all(np.abs(h - want) <= 4.5 * se + 1e-12 * want.sum()), (h, want, se)
+
+
+def test_mc_error_is_the_standard_error_of_the_weights(orc):
+    """Section 3.1 step 6: sigma is the mean of the per-point weights and its
+    error the standard error of that mean, std(w, ddof=1)/sqrt(N)."""
+    cfg = orc.Config(mode=0, seed=5, npoints=4096, sqrt_s=1000.0)
+    r = orc.xsec(3, cfg, want_weights=True)
+    w = r["w"]
+    assert (w > 0).sum() == r["n_acc"]
+    assert r["sigma_fb"] == pytest.approx(np.mean(w), rel=1e-12)
+    assert r["err_fb"] == pytest.approx(np.std(w, ddof=1) / math.sqrt(w.size), rel=1e-9)
+
+
+def test_mc_error_matches_the_spread_over_seeds(orc):
+    """The error estimate describes the scatter of sigma over independent
+    samples: over 64 seeds of 4096 points, the sample standard deviation of
+    sigma and the mean reported error agree (a dropped 1/(N-1) or square root
+    is off by a factor of at least sqrt(4095))."""
+    sig, err = [], []
+    for seed in range(100, 164):
+        r = orc.xsec(2, orc.Config(mode=0, seed=seed, npoints=4096, sqrt_s=500.0, pt_min=20.0,
+                                   eta_max=2.5, dr_min=0.0))
+        sig.append(r["sigma_fb"])
+        err.append(r["err_fb"])
+    ratio = np.std(sig, ddof=1) / np.mean(err)
+    assert 0.7 < ratio < 1.35, ratio
+    ref = pins.sigma_hat_n2(500.0 ** 2, ALPHA, Q, pins.cos_max_n2(500.0, 0.0, 20.0, 2.5))
+    assert abs(np.mean(sig) - ref) < 4.0 * np.mean(err) / 8.0  # 64 samples: error / 8
