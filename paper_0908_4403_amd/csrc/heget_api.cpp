@@ -894,9 +894,8 @@ heget_result make_result(const double *st, int64_t n_gen)
     return r;
 }
 
-// Capture the batch for one schedule into an executable graph.
-heget_status capture_batch(int schedule, int ncfg, const int *n, const heget_config *cfgs,
-                           double *staged, hipStream_t s, hipGraphExec_t *exec)
+// Bytes of the S_BATCH slot that the batch needs under one schedule.
+size_t batch_bytes(int schedule, int ncfg, const int *n, const heget_config *cfgs)
 {
     SliceBufs sb[heget::kMaxSlices];
     unsigned *flags;
@@ -904,8 +903,19 @@ heget_status capture_batch(int schedule, int ncfg, const int *n, const heget_con
     int64_t *item_start;
     Arena sizing;
     carve_batch(sizing, ncfg, n, cfgs, schedule, sb, &flags, &queue, &item_start);
-    void *base = nullptr;
-    HG_TRY(scratch(S_BATCH, sizing.off, &base));
+    return sizing.off;
+}
+
+// Capture the batch for one schedule into an executable graph, its buffers
+// carved from `base` (the S_BATCH slot, already at least batch_bytes long).
+// The graph keeps these addresses: the slot must not move while it lives.
+heget_status capture_batch(int schedule, int ncfg, const int *n, const heget_config *cfgs,
+                           void *base, double *staged, hipStream_t s, hipGraphExec_t *exec)
+{
+    SliceBufs sb[heget::kMaxSlices];
+    unsigned *flags;
+    unsigned long long *queue;
+    int64_t *item_start;
     Arena ar;
     ar.base = static_cast<char *>(base);
     carve_batch(ar, ncfg, n, cfgs, schedule, sb, &flags, &queue, &item_start);
@@ -1083,6 +1093,12 @@ heget_status heget_me2_device(int n, int64_t npoints, const double *d_mom, doubl
     HG_TRY(scratch_t<unsigned>(S_FLAGS, 1, &d_flags));
     HG_TRY(me2_on_device(n, npoints, d_mom, d_out, prec, s, d_flags));
     return HEGET_OK;
+}
+
+heget_status heget_me2_async(int n, int64_t npoints, const double *d_mom, double *d_out,
+                             heget_prec prec, heget_stream stream)
+{
+    return heget_me2_device(n, npoints, d_mom, d_out, prec, stream);
 }
 
 heget_status heget_helas_sizes(int func, int *in_doubles, int *out_doubles)
@@ -1354,22 +1370,39 @@ heget_status heget_xsec_batch(const int *n, const heget_config *cfgs, int ncfg,
         nb.key = key;
         HG_HIP(hipHostMalloc(reinterpret_cast<void **>(&nb.staged),
                              sizeof(double) * 4 * (heget::kMaxSlices + 1), hipHostMallocDefault));
-        if (g.batch_schedule == 0) {
+        // One S_BATCH slot of the size the largest schedule needs, obtained
+        // before any capture: growing the slot frees the old memory, which a
+        // graph captured earlier in this call would still address.
+        size_t need = batch_bytes(g.batch_schedule == 0 ? 1 : g.batch_schedule, ncfg, n, cfgs);
+        if (g.batch_schedule == 0) need = std::max(need, batch_bytes(2, ncfg, n, cfgs));
+        void *base = nullptr;
+        hipGraphExec_t a1 = nullptr, a2 = nullptr;
+        heget_status st = scratch(S_BATCH, need, &base);
+        if (st >= 0 && g.batch_schedule == 0) {
             // auto: capture both schedules, keep the faster (one timed run each)
-            hipGraphExec_t a1 = nullptr, a2 = nullptr;
-            HG_TRY(capture_batch(1, ncfg, n, cfgs, nb.staged, s, &a1));
-            HG_TRY(capture_batch(2, ncfg, n, cfgs, nb.staged, s, &a2));
-            HG_HIP(hipGraphLaunch(a1, s));  // warm both
-            HG_HIP(hipGraphLaunch(a2, s));
+            st = capture_batch(1, ncfg, n, cfgs, base, nb.staged, s, &a1);
+            if (st >= 0) st = capture_batch(2, ncfg, n, cfgs, base, nb.staged, s, &a2);
             float t1 = 0.f, t2 = 0.f;
-            HG_TRY(time_graph(a1, s, &t1));
-            HG_TRY(time_graph(a2, s, &t2));
-            nb.schedule = t1 <= t2 ? 1 : 2;
-            nb.exec = t1 <= t2 ? a1 : a2;
-            (void)hipGraphExecDestroy(t1 <= t2 ? a2 : a1);
-        } else {
+            if (st >= 0 && (hipGraphLaunch(a1, s) != hipSuccess || hipGraphLaunch(a2, s) != hipSuccess))
+                st = fail(HEGET_ERR_DEVICE, "hipGraphLaunch failed");  // the launches warm both
+            if (st >= 0) st = time_graph(a1, s, &t1);
+            if (st >= 0) st = time_graph(a2, s, &t2);
+            if (st >= 0) {
+                nb.schedule = t1 <= t2 ? 1 : 2;
+                nb.exec = t1 <= t2 ? a1 : a2;
+                (t1 <= t2 ? a1 : a2) = nullptr;
+            }
+        } else if (st >= 0) {
             nb.schedule = g.batch_schedule;
-            HG_TRY(capture_batch(nb.schedule, ncfg, n, cfgs, nb.staged, s, &nb.exec));
+            st = capture_batch(nb.schedule, ncfg, n, cfgs, base, nb.staged, s, &nb.exec);
+        }
+        if (st < 0) (void)hipStreamSynchronize(s);  // nothing of a failed call is left in flight
+        if (a1) (void)hipGraphExecDestroy(a1);
+        if (a2) (void)hipGraphExecDestroy(a2);
+        if (st < 0) {
+            if (nb.exec) (void)hipGraphExecDestroy(nb.exec);
+            (void)hipHostFree(nb.staged);
+            return st;
         }
         g_graphs.push_back(nb);
         bg = &g_graphs.back();

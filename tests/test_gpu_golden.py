@@ -122,7 +122,7 @@ def _full_size_sampled(H, orc, wl, prec, nsample, subsets):
 
 @pytest.mark.parametrize("prec", ["FP64", "FP32"])
 def test_full_size_4a_sampled(H, orc, prec):
-    from paper_0908_4403_amd.workloads import WORKLOADS
+    from workloads import WORKLOADS
     rel, nacc = _full_size_sampled(H, orc, WORKLOADS["uubar_4a_1TeV_2p20"], getattr(H, prec), 2000, False)
     print(prec, "n=4 full size", nacc, "survivors; sampled max rel", rel.max(), flush=True)
     if prec == "FP64":
@@ -133,7 +133,7 @@ def test_full_size_4a_sampled(H, orc, prec):
 
 @pytest.mark.parametrize("prec", ["FP64", "FP32"])
 def test_full_size_8a_sampled(H, orc, prec):
-    from paper_0908_4403_amd.workloads import WORKLOADS
+    from workloads import WORKLOADS
     rel, nacc = _full_size_sampled(H, orc, WORKLOADS["uubar_8a_2TeV_2p18"], getattr(H, prec), 256, True)
     print(prec, "n=8 full size", nacc, "survivors; sampled max rel", rel.max(), flush=True)
     if prec == "FP64":
@@ -145,7 +145,7 @@ def test_full_size_8a_sampled(H, orc, prec):
 def test_full_size_pp_5a_properties(H):
     """pp -> 5 photons, 2^22 points: deterministic, FP32 within 1e-5 of FP64,
     batch form equal to the single form."""
-    from paper_0908_4403_amd.workloads import WORKLOADS
+    from workloads import WORKLOADS
     wl = WORKLOADS["pp_5a_14TeV_2p22"]
     kw = dict(mode=wl["mode"], seed=wl["seed"], npoints=wl["npoints"], sqrt_s=wl["sqrt_s"],
               sqrt_shat_lo=wl["lo"], pt_min=wl["cuts"][0], eta_max=wl["cuts"][1], dr_min=wl["cuts"][2])
@@ -163,7 +163,7 @@ def test_full_size_pp_5a_properties(H):
 def test_full_size_mixed_batch_vs_single(H):
     """The mixed n = 2..7 workload in one batch equals one call per n (same
     points; the batch may run other kernel shapes, so FP32 agrees to the FP32 bar)."""
-    from paper_0908_4403_amd.workloads import MIXED_BATCH
+    from workloads import MIXED_BATCH
     cfgs = [H.Config(mode=s["mode"], prec=H.FP32, seed=s["seed"], npoints=s["npoints"],
                      sqrt_shat_lo=s["lo"], sqrt_shat_hi=s["hi"], pt_min=s["cuts"][0],
                      eta_max=s["cuts"][1], dr_min=s["cuts"][2]) for s in MIXED_BATCH]
@@ -173,3 +173,21 @@ def test_full_size_mixed_batch_vs_single(H):
         single = H.xsec(n, c)
         assert single["n_acc"] == b["n_acc"]
         assert abs(single["sigma_fb"] / b["sigma_fb"] - 1) < 1e-5, (n, single, b)
+
+
+def test_auto_batch_from_fresh_scratch(H):
+    """An n = 8 FP32 batch under the auto schedule on a library with no scratch
+    yet: the two schedules it captures need arenas of different sizes, and the
+    slot both are carved from is sized for the larger before either capture, so
+    the graph kept addresses live memory (regression: the second capture used
+    to grow, and free, the slot the first graph addressed)."""
+    g = read_xsec("xsec_uubar_8a_2TeV_first2p12.txt")
+    H.shutdown()
+    H.set_batch_schedule(H.BATCH_AUTO)
+    cfg = h_config(H, g, H.FP32)
+    (r,) = H.xsec_batch([8], [cfg])
+    (again,) = H.xsec_batch([8], [cfg])  # replay of the kept graph
+    print("fresh auto batch n=8:", r["sigma_fb"], g["sigma_fb"], flush=True)
+    assert r == again
+    assert r["n_gen"] == g["n_gen"] and r["n_acc"] == g["n_acc"]
+    assert abs(r["sigma_fb"] / g["sigma_fb"] - 1) < 1e-5
