@@ -39,7 +39,7 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PUBLISHED_FP32_VECTOR_TFLOPS = 157.3
 
 def _workloads():
-    from paper_0908_4403_amd.workloads import MIXED_BATCH, WORKLOADS
+    from workloads import MIXED_BATCH, WORKLOADS
     return WORKLOADS, MIXED_BATCH
 
 

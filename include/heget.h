@@ -133,6 +133,11 @@ heget_status heget_me2(int n, int64_t npoints, const double *momenta, double *ou
 heget_status heget_me2_device(int n, int64_t npoints, const double *d_mom, double *d_out,
                               heget_prec prec, heget_stream stream);
 
+/* The same call under the name of the stream-ordered form of heget_me2:
+ * identical arguments, layout, ownership and errors as heget_me2_device. */
+heget_status heget_me2_async(int n, int64_t npoints, const double *d_mom, double *d_out,
+                             heget_prec prec, heget_stream stream);
+
 /* Monte-Carlo cross section (Section 3.1 steps 2-6, eq. (1)-(2)): every
  * point is generated, cut, evaluated and weighted on the device; only the
  * result crosses to the host.  out (host) receives sigma +- err in fb.

@@ -37,6 +37,7 @@ FIXED_SHAT, UNIFORM_SQRTSHAT, PP_TOY = 0, 1, 2
 OBS_PT_MAX, OBS_DR_MIN = 0, 1
 
 EXPORTS = ["heget_gen_points", "heget_gen_points_device", "heget_me2", "heget_me2_device",
+           "heget_me2_async",
            "heget_xsec", "heget_xsec_async", "heget_xsec_device", "heget_xsec_hist",
            "heget_xsec_events",
            "heget_xsec_batch",
@@ -100,6 +101,7 @@ def _load():
     lib.heget_me2.argtypes = [C.c_int, C.c_int64, _dp, _dp, C.c_int]
     lib.heget_me2_device.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_int,
                                      C.c_void_p]
+    lib.heget_me2_async.argtypes = lib.heget_me2_device.argtypes
     lib.heget_xsec.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result)]
     lib.heget_xsec_async.argtypes = [C.c_int, C.POINTER(_Config), C.POINTER(Result), C.c_void_p]
     lib.heget_set_batch_schedule.argtypes = [C.c_int]
@@ -253,8 +255,12 @@ def xsec_batch(ns, cfgs, return_status: bool = False):
 
 def xsec_device(n: int, cfg: Config, out, stream=None) -> None:
     """Enqueue the cross section with its result record written by the device into
-    `out`: a torch uint8/int64 tensor of >= 56 bytes on the GPU or in pinned host
+    `out`: a contiguous torch tensor of >= 56 bytes on the GPU or in pinned host
     memory (layout of Result; read it back with result_from_bytes)."""
+    if out.numel() * out.element_size() < C.sizeof(Result) or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous tensor of at least {C.sizeof(Result)} bytes")
+    if not (out.is_cuda or _is_pinned(out)):
+        raise ValueError("out must be GPU memory or pinned host memory")
     c = cfg.c()
     _check(_lib.heget_xsec_device(n, C.byref(c), C.c_void_p(out.data_ptr()), _stream(stream)),
            "heget_xsec_device")
@@ -306,22 +312,30 @@ class XsecAsync:
 
 def me2_device(n: int, mom_soa, out, prec: int = FP32, stream=None) -> None:
     """|M|^2 of the points in mom_soa[(n+2)*4, npoints] (float64, GPU) into out[npoints]."""
-    if mom_soa.dtype != out.dtype or str(mom_soa.dtype) != "torch.float64":
-        raise TypeError("device buffers must be float64")
-    if not (mom_soa.is_cuda and out.is_cuda and mom_soa.is_contiguous() and out.is_contiguous()):
-        raise ValueError("device buffers must be contiguous GPU tensors")
-    if mom_soa.shape[0] != (n + 2) * 4 or out.shape[0] != mom_soa.shape[1]:
+    _device_f64(mom_soa, out)
+    if mom_soa.dim() != 2 or out.dim() != 1 or mom_soa.shape[0] != (n + 2) * 4 or out.shape[0] != mom_soa.shape[1]:
         raise ValueError("shape mismatch: mom_soa[(n+2)*4, npoints], out[npoints]")
     _check(_lib.heget_me2_device(n, mom_soa.shape[1], mom_soa.data_ptr(), out.data_ptr(), prec,
                                  _stream(stream)), "heget_me2_device")
 
 
+def me2_async(n: int, mom_soa, out, prec: int = FP32, stream=None) -> None:
+    """heget_me2_async: the stream-ordered form of me2, same arguments as me2_device."""
+    _device_f64(mom_soa, out)
+    if mom_soa.dim() != 2 or out.dim() != 1 or mom_soa.shape[0] != (n + 2) * 4 \
+            or out.shape[0] != mom_soa.shape[1]:
+        raise ValueError("shape mismatch: mom_soa[(n+2)*4, npoints], out[npoints]")
+    _check(_lib.heget_me2_async(n, mom_soa.shape[1], mom_soa.data_ptr(), out.data_ptr(), prec,
+                                _stream(stream)), "heget_me2_async")
+
+
 def gen_points_device(n: int, sqrt_s: float, mom_soa, weight, cuts=(20.0, 2.5, 0.4), seed: int = 0,
                       first: int = 0, stream=None) -> None:
-    if mom_soa.shape[0] != (n + 2) * 4 or weight.shape[0] != mom_soa.shape[1]:
+    """Points first..first+npoints-1 into mom_soa[(n+2)*4, npoints] and their
+    phase-space weights into weight[npoints] (float64, GPU)."""
+    _device_f64(mom_soa, weight)
+    if mom_soa.dim() != 2 or weight.dim() != 1 or mom_soa.shape[0] != (n + 2) * 4 or weight.shape[0] != mom_soa.shape[1]:
         raise ValueError("shape mismatch: mom_soa[(n+2)*4, npoints], weight[npoints]")
-    if not (mom_soa.is_cuda and weight.is_cuda and mom_soa.is_contiguous() and weight.is_contiguous()):
-        raise ValueError("device buffers must be contiguous GPU tensors")
     c = _cuts(cuts)
     _check(_lib.heget_gen_points_device(n, sqrt_s, C.byref(c) if c else None, seed, first,
                                         mom_soa.shape[1], mom_soa.data_ptr(), weight.data_ptr(),
@@ -457,10 +471,17 @@ def helas(func, records, prec: int = FP64) -> np.ndarray:
     return out
 
 
+def _is_pinned(t) -> bool:
+    try:
+        return bool(t.is_pinned())
+    except RuntimeError:  # no device runtime to ask: not pinned memory
+        return False
+
+
 def _device_f64(*ts) -> None:
+    if any(str(t.dtype) != "torch.float64" for t in ts):
+        raise TypeError("device buffers must be float64")
     for t in ts:
-        if str(t.dtype) != "torch.float64":
-            raise TypeError("device buffers must be float64")
         if not (t.is_cuda and t.is_contiguous()):
             raise ValueError("device buffers must be contiguous GPU tensors")
 

@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 import oracle as O  # noqa: E402
-from paper_0908_4403_amd.workloads import MIXED_BATCH, WORKLOADS  # noqa: E402
+from workloads import MIXED_BATCH, WORKLOADS  # noqa: E402
 
 
 def survivors(n, sqrt_s, seed, count, cuts):

@@ -169,3 +169,55 @@ def test_flop_count_of_every_shape():
                         assert 0.25 * ref < f < ref, (n, shape, f, ref)
             finally:
                 H.set_kernel_shape(n, prec, None)
+
+
+class _NoLib:
+    """Stands in for the library: any call reaching it fails the test."""
+
+    def __getattr__(self, name):
+        raise AssertionError(f"{name} was called although the binding should have refused")
+
+
+def test_device_calls_check_buffers_before_the_library(monkeypatch):
+    """Wrong dtypes, short or host result buffers are refused by the binding,
+    before a pointer reaches the library (a float32 buffer would be written
+    past its end by the FP64 kernels)."""
+    import torch
+    import paper_0908_4403_amd as H
+    monkeypatch.setattr(H, "_lib", _NoLib())
+    n, N = 4, 64
+    for mom, w in ((torch.zeros((n + 2) * 4, N, dtype=torch.float32), torch.zeros(N, dtype=torch.float64)),
+                   (torch.zeros((n + 2) * 4, N, dtype=torch.float64), torch.zeros(N, dtype=torch.float32))):
+        with pytest.raises(TypeError):
+            H.gen_points_device(n, 1000.0, mom, w)
+        with pytest.raises(TypeError):
+            H.me2_device(n, mom, w)
+        with pytest.raises(TypeError):
+            H.me2_async(n, mom, w)
+    f64 = dict(dtype=torch.float64)
+    with pytest.raises(ValueError):  # host tensors: not device memory
+        H.gen_points_device(n, 1000.0, torch.zeros((n + 2) * 4, N, **f64), torch.zeros(N, **f64))
+    with pytest.raises(ValueError):  # shorter than one result record
+        H.xsec_device(n, H.Config(), torch.zeros(6, **f64))
+    with pytest.raises(ValueError):  # pageable host memory: the device cannot write it
+        H.xsec_device(n, H.Config(), torch.zeros(7, **f64))
+    with pytest.raises(ValueError):  # not contiguous
+        H.xsec_device(n, H.Config(), torch.zeros(14, **f64)[::2])
+
+
+def test_me2_async_is_the_device_form():
+    import paper_0908_4403_amd as H
+    names = declared_functions()
+    assert "heget_me2_async" in names and "heget_me2_device" in names
+    assert H.lib().heget_me2_async(9, 1, None, None, 0, None) == H.ERR_RANGE
+    assert H.lib().heget_me2_async(4, 1, None, None, 0, None) == H.ERR_ARG
+    assert H.lib().heget_me2_async(4, 0, None, None, 0, None) == H.OK
+
+
+def test_golden_writer_imports_only_the_oracle():
+    """Stored expected values come from oracle/ alone: the writer never imports
+    the product package, and the workload table it shares is plain data."""
+    src = open(os.path.join(ROOT, "tests", "golden", "make_golden.py")).read()
+    assert "paper_0908_4403_amd" not in src
+    wl = open(os.path.join(ROOT, "workloads.py")).read()
+    assert not re.search(r"^\s*(import|from)\s", wl, flags=re.M)
