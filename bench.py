@@ -31,12 +31,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Issue-rate ceiling of the vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA)
-# x 2.4 GHz.  FP64 FMA and non-packed FP32 FMA issue at the same rate; the
-# library is built without packed-FP32 instructions, so this is the ceiling
-# for both precisions (the published 157.3 TFLOP/s FP32 figure needs packed FP32).
-PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-PUBLISHED_FP32_VECTOR_TFLOPS = 157.3
+# Published MI355X vector peaks (256 CUs at 2.4 GHz): the roofline denominators.
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+# One non-packed FMA per lane per clock (256 CUs x 4 SIMDs x 16 lanes x 2 flop
+# x 2.4 GHz), reported beside the published figure for reference only.
+NONPACKED_FMA_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def peak_of(prec_name):
+    return PEAK_FP32_VECTOR_TFLOPS if prec_name == "fp32" else PEAK_FP64_VECTOR_TFLOPS
+
 
 def _workloads():
     from workloads import MIXED_BATCH, WORKLOADS
@@ -162,7 +167,9 @@ def per_n(H, torch, tune):
             f, shape = H.me2_flops(n, prec)
             tf = f * npts / (ms * 1e-3) / 1e12
             row[name] = {"points_per_s": npts / (ms * 1e-3), "kernel_ms": ms, "tflops": tf,
-                         "frac": tf / PEAK_VALU_TFLOPS, "shape": shape, "flops_per_point": f}
+                         "frac": tf / peak_of(name), "peak": peak_of(name),
+                         "frac_of_nonpacked_fma": tf / NONPACKED_FMA_TFLOPS,
+                         "shape": shape, "flops_per_point": f}
         print(f"bench: per-n n={n} FP32 {row['fp32']['points_per_s']:.3e} pts/s "
               f"({row['fp32']['frac']:.2f}), FP64 {row['fp64']['points_per_s']:.3e} "
               f"({row['fp64']['frac']:.2f})", file=sys.stderr, flush=True)
@@ -191,31 +198,164 @@ def per_n(H, torch, tune):
     return out
 
 
-def cpu_baseline(n, wl, budget_s):
-    """FP64 oracle |M|^2 on the first survivors of the same stream (~budget_s of CPU)."""
+def cpu_model():
+    """Host CPU model name and clock (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    info = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    model = info.get("Model name")
+    mhz = info.get("CPU max MHz") or info.get("CPU MHz")
+    if (model is None or mhz is None) and os.path.exists("/proc/cpuinfo"):
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name") and model is None:
+                model = line.split(":", 1)[1].strip()
+            if line.startswith("cpu MHz") and mhz is None:
+                mhz = line.split(":", 1)[1].strip()
+    return {"model": model, "max_mhz": float(mhz) if mhz else None,
+            "logical_cpus": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def _survivors(O, n, sqrt_s, seed, cuts, count, start=0):
+    out = []
+    while len(out) < count:
+        ev = O.cm_events(n, sqrt_s, seed, start, 4 * count)
+        start += ev.shape[0]
+        out.extend(p for p in ev if O.pass_cuts(p[2:], 0.0, *cuts))
+    import numpy as np
+    return np.array(out[:count])
+
+
+def _error_stats(got, ref):
+    """Per-point relative error |got/ref - 1|: quantiles and a log10 histogram."""
+    import numpy as np
+    rel = np.abs(got / ref - 1.0)
+    edges = list(range(-17, -2))  # decades 1e-17 .. 1e-3
+    lg = np.log10(np.maximum(rel, 1e-300))
+    hist = {"below_1e-17": int(np.sum(lg < -17))}
+    for lo in edges[:-1]:
+        hist[f"1e{lo}..1e{lo + 1}"] = int(np.sum((lg >= lo) & (lg < lo + 1)))
+    hist["above_1e-3"] = int(np.sum(lg >= -3))
+    return {"points": int(rel.size), "median": float(np.median(rel)),
+            "p99": float(np.quantile(rel, 0.99)), "p99_9": float(np.quantile(rel, 0.999)),
+            "max": float(rel.max()), "nonfinite": int(np.sum(~np.isfinite(got))),
+            "log10_histogram": hist}
+
+
+def oracle_leg(H, n, wl, budget_s, golden_n8):
+    """The FP64 CPU oracle on the host cores: its throughput on a bounded
+    sample of the timed workload (all cores, then one core), and the per-point
+    error of the device |M|^2 (FP32 and FP64 amplitudes) against it for
+    n = 4..8 at the workloads' kinematics."""
     import numpy as np
     import oracle as O
 
-    def sample(count):
-        out, start = [], 0
-        while len(out) < count:
-            ev = O.cm_events(n, wl["sqrt_s"], wl["seed"], start, 4 * count)
-            start += ev.shape[0]
-            out.extend(p for p in ev if O.pass_cuts(p[2:], 0.0, *wl["cuts"]))
-        return np.array(out[:count])
-
-    cal = sample(256)
+    cuts = wl["cuts"]
+    cal = _survivors(O, n, wl["sqrt_s"], wl["seed"], cuts, 256)
     t0 = time.perf_counter()
     O.me2_batch(cal)
     dt = time.perf_counter() - t0
     count = int(min(max(256, budget_s / max(dt, 1e-6) * 256), 1 << 20))
-    ev = sample(count)
+    ev = _survivors(O, n, wl["sqrt_s"], wl["seed"], cuts, count)
     t0 = time.perf_counter()
-    _, threads = O.me2_batch(ev)
-    dt = time.perf_counter() - t0
-    return {"value": count / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 brute-force |M|^2 of the first {count} points passing the cuts "
-                      f"(seed {wl['seed']}, n={n}, sqrt(shat)={wl['sqrt_s']:.0f} GeV), {dt:.1f} s"}
+    ref, threads = O.me2_batch(ev)
+    dt_all = time.perf_counter() - t0
+    # one core, as the paper's single-threaded CPU program (first points of the same sample)
+    O.set_threads(1)
+    try:
+        rate1 = count / dt_all / max(threads, 1)
+        c1 = int(min(count, max(64, 0.5 * budget_s * rate1)))
+        t0 = time.perf_counter()
+        O.me2_batch(ev[:c1])
+        dt_one = time.perf_counter() - t0
+    finally:
+        O.set_threads(0)
+    base = {"value": count / dt_all, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 brute-force |M|^2 (all n! orderings x all helicities) of the first {count} "
+                      f"points passing the cuts (seed {wl['seed']}, n={n}, sqrt(shat)={wl['sqrt_s']:.0f} GeV), "
+                      f"{dt_all:.1f} s",
+            "one_core": {"value": c1 / dt_one, "unit": "points/s", "cores": 1,
+                         "sample": f"the first {c1} points of the same sample, {dt_one:.1f} s"},
+            "cpu": cpu_model()}
+
+    acc = {}
+
+    def record(key, pts, want, what):
+        row = {"what": what}
+        for prec, name in ((H.FP32, "fp32"), (H.FP64, "fp64")):
+            row[name] = _error_stats(H.me2(pts, prec), want)
+        acc[key] = row
+        print(f"bench: accuracy {key} FP32 median {row['fp32']['median']:.2e} p99.9 "
+              f"{row['fp32']['p99_9']:.2e}; FP64 max {row['fp64']['max']:.2e}", file=sys.stderr, flush=True)
+
+    record(f"n{n}", ev, ref, f"the cpu_baseline sample above ({count} points), brute-force oracle")
+    # n = 5..7 at sqrt(shat) = 1 TeV (seed 1, paper cuts): the oracle's subset
+    # recursion (equal to the brute-force sum, pinned by the oracle tests)
+    for m, cnt in ((5, 4096), (6, 2048), (7, 1024)):
+        if m == n:
+            continue
+        pts = _survivors(O, m, 1000.0, 1, cuts, cnt)
+        want, _ = O.me2_subsets_batch(pts)
+        record(f"n{m}", pts, want, f"first {cnt} points passing the cuts, n={m}, sqrt(shat)=1 TeV, seed 1, "
+                                   "oracle subset recursion")
+    # n = 8: the stored oracle values of the first 1024 survivors of the n = 8 workload
+    if golden_n8 and os.path.exists(golden_n8):
+        idx, want = [], []
+        for line in open(golden_n8):
+            if line.strip() and not line.startswith("#"):
+                a, b = line.split()
+                idx.append(int(a))
+                want.append(float(b))
+        pts = np.array([O.cm_event(8, 2000.0, 4, i) for i in idx])
+        record("n8", pts, np.array(want), f"first {len(idx)} survivors of the n=8 workload (2 TeV, seed 4), "
+                                          "stored oracle values (tests/golden)")
+    return base, acc
+
+
+def config_n8(H, torch, wl, reps):
+    """The n = 8 workload end to end (2^18 points at 2 TeV, paper cuts): FP32 and
+    FP64 amplitudes, whole pass and amplitude kernel timed (HIP events on the
+    launch stream), with the kernel's roofline against the published peak."""
+    n = wl["n"]
+    base = dict(mode=wl["mode"], seed=wl["seed"], npoints=wl["npoints"], sqrt_s=wl["sqrt_s"],
+                pt_min=wl["cuts"][0], eta_max=wl["cuts"][1], dr_min=wl["cuts"][2])
+    out = {"workload": "uubar_8a_2TeV_2p18", "process": "u ubar -> 8 photons", "sqrt_shat_GeV": wl["sqrt_s"],
+           "points_generated": wl["npoints"], "seed": wl["seed"],
+           "cuts": "pT>%g GeV, |eta|<%g, dR>%g" % tuple(wl["cuts"])}
+    for prec, name in ((H.FP32, "fp32"), (H.FP64, "fp64")):
+        cfg = H.Config(prec=prec, **base)
+        buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
+        H.xsec_device(n, cfg, buf)  # sizes scratch, raises the clock
+        torch.cuda.synchronize()
+        H.timing_enable(True)
+        H.timing_read(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            H.xsec_device(n, cfg, buf)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        kms, launches = H.timing_read(reset=True)
+        H.timing_enable(False)
+        kms /= max(launches, 1)
+        r = H.result_from_bytes(buf.cpu().numpy())
+        f, shape = H.me2_flops(n, prec)
+        ach = f * r["n_acc"] / (kms * 1e-3) / 1e12
+        out[name] = {"points_per_s": r["n_acc"] / dt, "ms_per_pass": dt * 1e3, "points_evaluated": r["n_acc"],
+                     "sigma_fb": r["sigma_fb"], "sigma_err_fb": r["err_fb"],
+                     "roofline": {"bound": "alu", "achieved": ach, "peak": peak_of(name), "unit": "TFLOP/s",
+                                  "frac": ach / peak_of(name), "kernel": "me2_kernel<{},8,{}>".format(
+                                      "float" if name == "fp32" else "double",
+                                      ",".join(str(v) for v in shape)),
+                                  "kernel_ms": kms, "flops_per_point": f}}
+        print(f"bench: n=8 workload {name} {dt * 1e3:.1f} ms/pass, kernel {kms:.1f} ms, "
+              f"{r['n_acc'] / dt:.3e} pts/s, frac {ach / peak_of(name):.2f}", file=sys.stderr, flush=True)
+    out["fp32_over_fp64"] = out["fp32"]["points_per_s"] / out["fp64"]["points_per_s"]
+    return out
 
 
 def main():
@@ -227,15 +367,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--workload", default="uubar_4a_1TeV_2p20")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU baseline and per-point accuracy)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed n=2..7 batch")
+    ap.add_argument("--no-n8", action="store_true", help="skip the n=8 workload (2^18 points at 2 TeV)")
+    ap.add_argument("--no-per-n", action="store_true", help="skip the per-n amplitude kernel timings")
     ap.add_argument("--no-tune", action="store_true", help="use the untuned kernel shapes")
-    ap.add_argument("--settle-ms", type=float, default=300.0,
+    ap.add_argument("--settle-ms", type=float, default=1000.0,
                     help="untimed passes for this long before the warmup steps (clock ramp-up)")
-    ap.add_argument("--streams", type=int, default=3,
+    ap.add_argument("--streams", type=int, default=1,
                     help="consecutive steps go to this many streams in turn (1: one stream)")
-    ap.add_argument("--per-n", action="store_true",
-                    help="also time the amplitude kernel alone for n = 2..8 (FP32 and FP64)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for rocprofv3 FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -273,11 +414,7 @@ def main():
     settle(H, torch, n, H.Config(prec=H.FP32, **base), args.settle_ms)
     ms32, k32, l32, r32 = run_steps(H, torch, n, H.Config(prec=H.FP32, **base), args.steps, args.warmup,
                                     args.streams)
-    ms32_one = ms32
-    if args.streams > 1:
-        ms32_one = run_steps(H, torch, n, H.Config(prec=H.FP32, **base), args.steps, 1, 1)[0]
-    print(f"bench: FP32 {ms32:.3f} ms/step ({ms32_one:.3f} on one stream), me2 kernel {k32:.3f} ms",
-          file=sys.stderr, flush=True)
+    print(f"bench: FP32 {ms32:.3f} ms/step, me2 kernel {k32:.3f} ms", file=sys.stderr, flush=True)
     ms64, k64, l64, r64 = run_steps(H, torch, n, H.Config(prec=H.FP64, **base),
                                     max(3, args.steps // 2), 1, args.streams)
     print(f"bench: FP64 {ms64:.3f} ms/step, me2 kernel {k64:.3f} ms", file=sys.stderr, flush=True)
@@ -295,15 +432,17 @@ def main():
         print(f"bench: mixed batch {mixed['batch_ms']:.2f} ms vs per-n {mixed['one_launch_per_n_ms']:.2f} ms",
               file=sys.stderr, flush=True)
 
-    pern = per_n(H, torch, not args.no_tune) if args.per_n else None
+    pern = None if args.no_per_n else per_n(H, torch, not args.no_tune)
+    n8 = None if args.no_n8 else config_n8(H, torch, workloads["uubar_8a_2TeV_2p18"], 1)
 
-    cpu = None
+    cpu, accuracy = None, None
     if not args.no_cpu_baseline:
-        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(n, wl, args.cpu_seconds)
+        print("bench: oracle leg (cpu baseline, per-point accuracy)", file=sys.stderr, flush=True)
+        golden = os.path.join(ROOT, "tests", "golden", "me2_n8_2TeV_seed4_subsets.txt")
+        cpu, accuracy = oracle_leg(H, n, wl, args.cpu_seconds, golden)
 
     peak = H.valu_peak()
-    print(f"bench: measured FMA ceiling FP32 {peak['fp32_tflops']:.1f}, FP64 {peak['fp64_tflops']:.1f} TFLOP/s",
+    print(f"bench: FMA probe FP32 {peak['fp32_tflops']:.1f}, FP64 {peak['fp64_tflops']:.1f} TFLOP/s",
           file=sys.stderr, flush=True)
     kname = "me2_kernel<float,{},{}>".format(n, ",".join(str(v) for v in shape32))
     from paper_0908_4403_amd.profiling import read_traffic
@@ -324,28 +463,32 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "process": f"u ubar -> {n} photons",
-                   "streams": args.streams, "settle_ms": args.settle_ms, "ms_per_step_one_stream": ms32_one,
+                   "streams": args.streams, "settle_ms": args.settle_ms,
                    "sqrt_shat_GeV": wl["sqrt_s"], "points_generated": wl["npoints"],
                    "points_evaluated": n_acc, "seed": wl["seed"],
                    "cuts": "pT>%g GeV, |eta|<%g, dR>%g" % tuple(wl["cuts"]), "sigma_fb": r32["sigma_fb"],
                    "sigma_err_fb": r32["err_fb"]},
-        "roofline": {"bound": "alu", "achieved": ach32, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach32 / PEAK_VALU_TFLOPS, "traffic": traffic,
+        "roofline": {"bound": "alu", "achieved": ach32, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach32 / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": kname,
                      "kernel_ms": k32,
-                     "flops_per_point": f32, "frac_of_published_fp32_vector": ach32 / PUBLISHED_FP32_VECTOR_TFLOPS,
-                     "measured_fma_ceiling": peak["fp32_tflops"],
-                     "frac_of_measured_ceiling": ach32 / peak["fp32_tflops"]},
+                     "kernel_share_of_step": k32 / ms32,
+                     "flops_per_point": f32,
+                     "frac_of_nonpacked_fma": ach32 / NONPACKED_FMA_TFLOPS,
+                     "fma_probe_tflops": peak["fp32_tflops"]},
         "fp64_plain": {"value": r64["n_acc"] / (ms64 * 1e-3), "ms_per_step": ms64, "kernel_ms": k64,
-                       "achieved_tflops": ach64, "frac": ach64 / PEAK_VALU_TFLOPS,
-                       "frac_of_measured_ceiling": ach64 / peak["fp64_tflops"],
+                       "achieved_tflops": ach64, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                       "frac": ach64 / PEAK_FP64_VECTOR_TFLOPS,
+                       "fma_probe_tflops": peak["fp64_tflops"],
                        "sigma_fb": r64["sigma_fb"], "flops_per_point": f64},
         "fp32_over_fp64": (n_acc / ms32) / (r64["n_acc"] / ms64),
         "generated_points_per_s": wl["npoints"] / (ms32 * 1e-3),
         "tuned_shapes": tuned,
-        "mixed_batch": mixed,
+        "n8_workload": n8,
         "per_n": pern,
+        "mixed_batch": mixed,
+        "accuracy_vs_oracle": accuracy,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -69,6 +69,8 @@ def lib():
                                    _dp, _dp]
         L.orc_me2.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, C.c_int]
         L.orc_me2.restype = C.c_double
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = C.c_int
         L.orc_me2_batch.argtypes = [C.c_int, C.c_int64, _dp, C.c_double, C.c_double, _dp]
         L.orc_me2_batch.restype = C.c_int
         L.orc_me2_subsets.argtypes = [C.c_int, _dp, C.c_double, C.c_double]
@@ -223,6 +225,11 @@ def me2(p, alpha: float = ALPHA, charge: float = CHARGE_U, skip_zero: bool = Tru
     p = _f64(p)
     return lib().orc_me2(p.shape[0] - 2, _ptr(p), alpha, charge, int(skip_zero),
                          int(u_along_minus_z))
+
+
+def set_threads(k: int) -> int:
+    """Threads of the batch functions from now on (k <= 0: the OpenMP default)."""
+    return lib().orc_set_threads(int(k))
 
 
 def me2_batch(p_aos, alpha: float = ALPHA, charge: float = CHARGE_U):

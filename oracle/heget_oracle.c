@@ -750,6 +750,21 @@ double orc_me2(int n, const double *p, double alpha, double charge, int skip_zer
     return sum;
 }
 
+/* Number of OpenMP threads the batch functions use from now on (k >= 1);
+ * k <= 0 restores the runtime default.  Returns the count in effect. */
+int orc_set_threads(int k)
+{
+#ifdef _OPENMP
+    static int deflt = 0;
+    if (deflt == 0) deflt = omp_get_max_threads();
+    omp_set_num_threads(k >= 1 ? k : deflt);
+    return omp_get_max_threads();
+#else
+    (void)k;
+    return 1;
+#endif
+}
+
 int orc_me2_batch(int n, int64_t np, const double *p_aos, double alpha, double charge,
                   double *out)
 {

@@ -93,6 +93,8 @@ void orc_amp_meet(int n, const double *p, int h1, int h2, const int *lam, double
 double orc_me2(int n, const double *p, double alpha, double charge, int skip_zero,
                int u_along_minus_z);
 /* OpenMP batch over points: p_aos[np][n+2][4] -> out[np]; returns threads used. */
+/* OpenMP threads of the batch functions (k <= 0: the default); returns it. */
+int orc_set_threads(int k);
 int orc_me2_batch(int n, int64_t np, const double *p_aos, double alpha, double charge,
                   double *out);
 /* Same |M|^2 by the subset (Berends-Giele) recursion of the same currents:
