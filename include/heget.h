@@ -157,6 +157,23 @@ heget_status heget_xsec_async(int n, const heget_config *cfg, heget_result *out,
 heget_status heget_xsec_device(int n, const heget_config *cfg, heget_result *d_out,
                                heget_stream stream);
 
+/* heget_xsec_device for callers that cannot allocate device memory (code
+ * under stream capture, serving loops, harnesses that forbid hipMalloc): the
+ * same pass, same arguments and same results, with every intermediate buffer
+ * (momenta, weights, survivor list, partial sums) carved from a fixed 64 MiB
+ * workspace that the library holds in a static device array, one per device,
+ * kept until the process ends.  The call allocates nothing (no hipMalloc,
+ * hipFree or pinned host memory).  A configuration whose buffers exceed the
+ * workspace -- about 32 (n + 2) + 14 bytes per point, e.g. 3.2e5 points at
+ * n = 4 or 2.0e5 at n = 8 -- returns HEGET_ERR_RANGE before anything is
+ * enqueued.  Every call on one device shares that device's workspace: calls
+ * that overlap on the device (concurrent streams, or a captured graph
+ * replayed beside another call) race and give wrong results; calls ordered
+ * on one stream are safe.  Nothing in the workspace needs to be cleared by
+ * the caller. */
+heget_status heget_xsec_device_noalloc(int n, const heget_config *cfg, heget_result *d_out,
+                                       heget_stream stream);
+
 /* Event observables for heget_xsec_hist (the distributions of Fig. 2). */
 typedef enum {
     HEGET_OBS_PT_MAX = 0, /* largest photon pT [GeV] */

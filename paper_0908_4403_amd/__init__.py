@@ -38,7 +38,8 @@ OBS_PT_MAX, OBS_DR_MIN = 0, 1
 
 EXPORTS = ["heget_gen_points", "heget_gen_points_device", "heget_me2", "heget_me2_device",
            "heget_me2_async",
-           "heget_xsec", "heget_xsec_async", "heget_xsec_device", "heget_xsec_hist",
+           "heget_xsec", "heget_xsec_async", "heget_xsec_device", "heget_xsec_device_noalloc",
+           "heget_xsec_hist",
            "heget_xsec_events",
            "heget_xsec_batch",
            "heget_set_batch_schedule", "heget_batch_schedule_in_use",
@@ -110,6 +111,7 @@ def _load():
     lib.heget_batch_schedule_in_use.argtypes = [C.POINTER(C.c_int), C.POINTER(_Config), C.c_int,
                                                 C.POINTER(C.c_int)]
     lib.heget_xsec_device.argtypes = [C.c_int, C.POINTER(_Config), C.c_void_p, C.c_void_p]
+    lib.heget_xsec_device_noalloc.argtypes = lib.heget_xsec_device.argtypes
     lib.heget_xsec_batch.argtypes = [C.POINTER(C.c_int), C.POINTER(_Config), C.c_int,
                                      C.POINTER(Result)]
     lib.heget_set_couplings.argtypes = [C.c_double, C.c_double]
@@ -264,6 +266,19 @@ def xsec_device(n: int, cfg: Config, out, stream=None) -> None:
     c = cfg.c()
     _check(_lib.heget_xsec_device(n, C.byref(c), C.c_void_p(out.data_ptr()), _stream(stream)),
            "heget_xsec_device")
+
+
+def xsec_device_noalloc(n: int, cfg: Config, out, stream=None) -> None:
+    """heget_xsec_device_noalloc: xsec_device on the library's fixed static
+    workspace (no device allocation); same arguments.  Raises (ERR_RANGE) when
+    the configuration's buffers exceed that workspace."""
+    if out.numel() * out.element_size() < C.sizeof(Result) or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous tensor of at least {C.sizeof(Result)} bytes")
+    if not (out.is_cuda or _is_pinned(out)):
+        raise ValueError("out must be GPU memory or pinned host memory")
+    c = cfg.c()
+    _check(_lib.heget_xsec_device_noalloc(n, C.byref(c), C.c_void_p(out.data_ptr()), _stream(stream)),
+           "heget_xsec_device_noalloc")
 
 
 def result_from_bytes(buf) -> dict:

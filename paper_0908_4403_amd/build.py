@@ -23,6 +23,7 @@ BUILD_DIR = os.path.join(PKG, "_build")
 SOURCES = ["me2_shapes_f32_lo.hip", "me2_shapes_f32_mid.hip", "me2_shapes_f32_hi.hip",
            "me2_shapes_f64_lo.hip", "me2_shapes_f64_mid.hip", "me2_shapes_f64_hi.hip",
            "me2_shapes_sampled.hip", "me2_batch.hip", "me2_registry.cpp", "mc_kernels.hip", "peak.hip", "helas_kernels.hip",
+           "static_scratch.hip",
            "heget_api.cpp"]
 ARCH = os.environ.get("HEGET_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

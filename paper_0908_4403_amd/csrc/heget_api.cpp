@@ -962,6 +962,29 @@ heget_status time_graph(hipGraphExec_t exec, hipStream_t s, float *ms)
     return HEGET_OK;
 }
 
+// Buffers of one cross-section pass carved from `ar` (a dry run with a null
+// base measures the bytes needed).
+void carve_static(int n, const heget_config &c, const heget::Me2Variant &v, Arena &ar, McBufs &b,
+                  unsigned **flags)
+{
+    const int64_t np = c.npoints;
+    const bool sampled = c.helicity_sampling != 0;
+    b = McBufs{};
+    b.nchunks = sampled ? 1 : plan_chunks(v, np / 2);
+    *flags = ar.take<unsigned>(1);
+    b.d_count = ar.take<int64_t>(1);
+    b.res = ar.take<double>(8);
+    b.mom = ar.take<double>(size_t(n + 2) * 4 * size_t(np));
+    b.wfac = ar.take<double>(size_t(np));
+    b.flag = ar.take<uint8_t>(size_t(np));
+    b.bcount = ar.take<int32_t>(size_t((np + 255) / 256));
+    b.index = ar.take<int32_t>(size_t(np));
+    b.hel = sampled ? ar.take<uint16_t>(size_t(np)) : nullptr;
+    b.wout = nullptr;
+    b.part = b.nchunks > 1 ? ar.take<double>(size_t(b.nchunks) * size_t(np)) : nullptr;
+    b.partials = ar.take<double>(size_t(3) * size_t((np + 63) / 64));
+}
+
 }  // namespace
 
 // ==================================================================== C ABI
@@ -1245,6 +1268,40 @@ heget_status heget_xsec_device(int n, const heget_config *cfg, heget_result *d_o
     std::lock_guard<std::mutex> lk(g_mu);
     HG_TRY(ensure_device());
     return xsec_enqueue(n, cfg, nullptr, d_out, static_cast<hipStream_t>(stream), nullptr);
+}
+
+heget_status heget_xsec_device_noalloc(int n, const heget_config *cfg, heget_result *d_out,
+                                       heget_stream stream)
+{
+    g_err.clear();
+    HG_TRY(check_config(n, cfg));
+    if (!d_out) return fail(HEGET_ERR_ARG, "d_out is NULL");
+    if (cfg->npoints == 0) return fail(HEGET_ERR_RANGE, "heget_xsec_device_noalloc needs npoints > 0");
+    const bool sampled = cfg->helicity_sampling != 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    const heget::Me2Variant *v =
+        sampled ? heget::me2_sampled(cfg->prec, n) : pick_variant(cfg->prec, n);
+    if (!v) return fail(HEGET_ERR_ARG, "no compiled amplitude kernel for this n/precision");
+    McBufs b;
+    unsigned *flags = nullptr;
+    Arena dry;
+    carve_static(n, *cfg, *v, dry, b, &flags);
+    const size_t cap = heget::static_scratch_bytes();
+    if (dry.off > cap)
+        return fail(HEGET_ERR_RANGE, "heget_xsec_device_noalloc: n = " + std::to_string(n) + " with " +
+                                         std::to_string(cfg->npoints) + " points needs " +
+                                         std::to_string(dry.off) + " bytes of workspace, above its " +
+                                         std::to_string(cap) + "-byte static workspace");
+    void *base = nullptr;
+    HG_HIP(heget::static_scratch_ptr(&base));
+    Arena ar;
+    ar.base = static_cast<char *>(base);
+    carve_static(n, *cfg, *v, ar, b, &flags);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HG_TRY(enqueue_generation(n, *cfg, b, s, flags));  // also clears flags
+    HG_HIP(heget::launch_me2(*v, mc_me2_args(n, *cfg, b, flags), s));
+    HG_TRY(enqueue_reduction(*cfg, b, flags, d_out, s));
+    return HEGET_OK;
 }
 
 heget_status heget_xsec(int n, const heget_config *cfg, heget_result *out)

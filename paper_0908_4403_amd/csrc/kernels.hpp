@@ -154,4 +154,9 @@ hipError_t launch_me2_frame(int n, int prec, int64_t np, const double *mom, int6
 // Zero a small device buffer with a kernel (usable under stream capture).
 hipError_t launch_zero_u32(unsigned *p, int count, hipStream_t stream);
 
+// Fixed-size device workspace of static_scratch.hip: its size in bytes, and
+// its device address on the current device (looked up once per device).
+size_t static_scratch_bytes();
+hipError_t static_scratch_ptr(void **ptr);
+
 }  // namespace heget
