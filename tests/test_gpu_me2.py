@@ -7,6 +7,8 @@ Sizes span several 64-point tiles plus a ragged tail.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import pytest
 
@@ -117,20 +119,38 @@ def test_me2_device_matches_host(H, orc):
         assert np.array_equal(out.cpu().numpy(), host)
 
 
+def _golden_n8(orc, count):
+    """The first `count` points of the stored n = 8 oracle values (2 TeV, seed 4)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "me2_n8_2TeV_seed4_subsets.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")][:count]
+    ev = np.array([orc.cm_event(8, 2000.0, 4, int(i)) for i, _ in rows])
+    return ev, np.array([float(v) for _, v in rows])
+
+
 @pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 7, 8])
 def test_every_compiled_shape_matches_oracle(H, orc, n):
     """Each unrolled depth / helicities-per-walk / waves-per-block shape the
-    autotuner may pick gives the oracle's |M|^2 (FP64 shapes to 1e-12)."""
-    count = {2: 200, 3: 130, 4: 70, 5: 67, 6: 20, 7: 3, 8: 1}[n]
-    ev = cut_events(orc, n, 1200.0, 300 + n, count)
-    ref = (orc.me2_subsets_batch(ev) if n >= 7 else orc.me2_batch(ev))[0]
+    autotuner may pick gives the oracle's |M|^2 (FP64 shapes to 1e-12, FP32 at
+    the median / 99.9th-percentile bars).  n = 7 and 8 run on 300 points (four
+    full tiles and a ragged fifth), so waves of a four-wave block each hold
+    different points and the per-lane LDS photon tables are exercised."""
+    count = {2: 200, 3: 130, 4: 70, 5: 67, 6: 20, 7: 300, 8: 300}[n]
+    if n == 8:
+        ev, ref = _golden_n8(orc, count)
+    else:
+        ev = cut_events(orc, n, 1200.0, 300 + n, count)
+        ref = (orc.me2_subsets_batch(ev) if n >= 7 else orc.me2_batch(ev))[0]
     try:
         for prec in (H.FP64, H.FP32):
             for shape in H.kernel_shapes(n, prec):
                 H.set_kernel_shape(n, prec, shape)
+                print(f"shape n={n} prec={prec} {shape} on {count} points", flush=True)
                 rel = np.abs(H.me2(ev, prec) / ref - 1)
-                bound = 1e-12 if prec == H.FP64 else 1e-3
-                assert rel.max() <= bound, (n, prec, shape, rel.max())
+                if prec == H.FP64:
+                    assert rel.max() <= 1e-12, (n, shape, rel.max())
+                else:
+                    assert np.median(rel) <= 1e-5 and np.quantile(rel, 0.999) <= 1e-3, \
+                        (n, shape, np.median(rel), rel.max())
     finally:
         H.set_kernel_shape(n, H.FP64)
         H.set_kernel_shape(n, H.FP32)
