@@ -263,15 +263,22 @@ heget_status heget_timing_read(double *me2_ms, int64_t *me2_launches, int reset)
  *                        3: as 2, and the two photons before them are summed
  *                        over both orders at the ubar end, where the two
  *                        currents share their propagator, so four photons
- *                        close with 6 pair products instead of 12
+ *                        close with 6 pair products instead of 12 (in FP32
+ *                        kernels with 8 or more helicities per walk each of
+ *                        the 6 products is taken in FP64); 4: as 3 with the
+ *                        products always in the working precision
  *   waves_per_block      64-lane waves per workgroup
  *   prefetch             0: one wave per 64-point work item; 1: only as many
  *                        waves as the device holds at once, each looping over
  *                        its items and loading the next item's inputs before
  *                        the walk of the current one (hides the memory latency
- *                        when few waves fit per SIMD, and shortens the tail) */
+ *                        when few waves fit per SIMD, and shortens the tail)
+ *   waves_per_simd       0: registers as the compiler likes; k > 0: at most
+ *                        512 / k registers per lane so that k waves share each
+ *                        SIMD (its FP32 instructions then issue from two waves
+ *                        at once) */
 typedef struct {
-    int32_t unrolled, helicities_per_walk, closing, waves_per_block, prefetch;
+    int32_t unrolled, helicities_per_walk, closing, waves_per_block, prefetch, waves_per_simd;
 } heget_shape;
 
 /* Algorithmic floating-point operations per point of the amplitude kernel

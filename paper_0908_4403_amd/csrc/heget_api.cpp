@@ -305,25 +305,25 @@ const heget::Me2Variant *pick_variant(int prec, int n)
     return heget::me2_default(prec, n);
 }
 
-const heget::Me2Variant *find_variant(int prec, int n, int mb, int h, int cl, int wpb, int pf)
+const heget::Me2Variant *find_variant(int prec, int n, int mb, int h, int cl, int wpb, int pf, int wpe)
 {
     int cnt = 0;
     const heget::Me2Variant *v = heget::me2_variants(&cnt);
     for (int i = 0; i < cnt; ++i)
         if (v[i].prec == prec && v[i].n == n && v[i].mb == mb && v[i].h == h && v[i].cl == cl &&
-            v[i].wpb == wpb && v[i].pf == pf)
+            v[i].wpb == wpb && v[i].pf == pf && v[i].wpe == wpe)
             return &v[i];
     return nullptr;
 }
 
 heget_shape shape_of(const heget::Me2Variant &v)
 {
-    return heget_shape{v.mb, v.h, v.cl, v.wpb, v.pf};
+    return heget_shape{v.mb, v.h, v.cl, v.wpb, v.pf, v.wpe};
 }
 
 // Tuning cache: one JSON object per line,
-// {"arch": "gfx950", "prec": 1, "n": 4, "mb": 4, "h": 2, "cl": 2, "wpb": 4, "pf": 0, "ms": 0.48,
-//  "points": 1048576}
+// {"arch": "gfx950", "prec": 1, "n": 4, "mb": 4, "h": 2, "cl": 2, "wpb": 4, "pf": 0, "wpe": 2,
+//  "ms": 0.48, "points": 1048576}
 void load_tuning_cache()
 {
     const char *path = std::getenv("HEGET_TUNING_CACHE");
@@ -333,11 +333,11 @@ void load_tuning_cache()
     char line[512];
     while (std::fgets(line, sizeof line, f)) {
         char arch[64] = {0};
-        int prec, n, mb, h, cl, wpb, pf;
-        if (std::sscanf(line, " {\"arch\": \"%63[^\"]\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d",
-                        arch, &prec, &n, &mb, &h, &cl, &wpb, &pf) == 8 &&
+        int prec, n, mb, h, cl, wpb, pf, wpe;
+        if (std::sscanf(line, " {\"arch\": \"%63[^\"]\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d, \"wpe\": %d",
+                        arch, &prec, &n, &mb, &h, &cl, &wpb, &pf, &wpe) == 9 &&
             g_arch == arch && prec >= 0 && prec < 2 && n >= 2 && n <= 8) {
-            const heget::Me2Variant *v = find_variant(prec, n, mb, h, cl, wpb, pf);
+            const heget::Me2Variant *v = find_variant(prec, n, mb, h, cl, wpb, pf, wpe);
             if (v) g_tuned[prec][n] = v;
         }
     }
@@ -360,8 +360,8 @@ void save_tuning_cache(const heget::Me2Variant &v, double ms, int64_t points)
     }
     if (FILE *f = std::fopen(path, "w")) {
         for (const std::string &l : keep) std::fputs(l.c_str(), f);
-        std::fprintf(f, "{\"arch\": \"%s\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d, \"ms\": %.6f, \"points\": %lld}\n",
-                     g_arch.c_str(), v.prec, v.n, v.mb, v.h, v.cl, v.wpb, v.pf, ms, static_cast<long long>(points));
+        std::fprintf(f, "{\"arch\": \"%s\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d, \"wpe\": %d, \"ms\": %.6f, \"points\": %lld}\n",
+                     g_arch.c_str(), v.prec, v.n, v.mb, v.h, v.cl, v.wpb, v.pf, v.wpe, ms, static_cast<long long>(points));
         std::fclose(f);
     }
 }
@@ -377,15 +377,21 @@ void save_tuning_cache(const heget::Me2Variant &v, double ms, int64_t points)
 // vector 2^(number of variant photons it involves).  Where the photons sit in
 // run-time slots (n > mb) nothing is shared and every value is counted h
 // times.  This is what the code computes when the compiler shares every
-// such value, so the count is a lower bound of the work executed.
+// such value, so the count is a lower bound of the work executed.  Vertex
+// blocks are normalised to a unit diagonal, so a vertex product is four
+// two-term fused multiply-adds on the current.
 //   node update: q update 4, q^2 5, 1/q^2 1, scale by d 4 (= 14, once per node)
-//                + 40 per distinct current (8 three-term complex products)
-//   cl = 1 leaf: closing 10 + 2 FP64 adds per helicity
+//                + 36 per distinct current (vertex half 16, propagator half 20)
+//   cl = 1 leaf: closing 8 + 2 FP64 adds per helicity
 //   cl = 2, node with two photons left: 2-vector product 14 + 2 FP64 adds per
 //         helicity; per subtree: per slot r, p1 - k_r 2, q^2 5, 1/q^2 1,
-//         scale 4 (= 12) and w_r 14 per distinct value, per ordered pair u_jr 20,
+//         scale 4 (= 12) and w_r 11 per distinct value, per ordered pair u_jr 16,
 //         per unordered pair U 4, per distinct value
-//   vertex block build: 3 + 4 per distinct value
+//   cl = 3, 4, node with four photons left: four node updates, then per split
+//         the propagator of q + k_x + k_y 14, per distinct value a vertex half
+//         16, a second vertex half added to it 20 and a propagator half 20,
+//         and a pair closing (16 per helicity)
+//   vertex block build: 4 per photon (kappa / k+-, shared by all helicities)
 //   |ordering sum|^2 in FP64: 4 per helicity
 namespace flops {
 
@@ -403,11 +409,11 @@ struct Walk {
     void subtree_pairs(unsigned slots)
     {
         for (int r = 0; r < n; ++r)
-            if (slots >> r & 1u) total += 12.0 + 14.0 * var_count(1u << r);
+            if (slots >> r & 1u) total += 12.0 + 11.0 * var_count(1u << r);
         for (int j = 0; j < n; ++j)
             for (int r = 0; r < n; ++r)
                 if (j != r && (slots >> j & 1u) && (slots >> r & 1u))
-                    total += 20.0 * var_count((1u << j) | (1u << r));
+                    total += 16.0 * var_count((1u << j) | (1u << r));
         for (int j = 0; j < n; ++j)
             for (int r = j + 1; r < n; ++r)
                 if ((slots >> j & 1u) && (slots >> r & 1u))
@@ -423,34 +429,34 @@ struct Walk {
         if (nleft == mb || (used == 0 && n <= mb)) {
             // subtree entry: vertex blocks of its slots, pair vectors
             for (int s = 0; s < n; ++s)
-                if (left >> s & 1u) total += 3.0 + 4.0 * var_count(1u << s);
+                if (left >> s & 1u) total += 4.0;
             if (cl >= 2) subtree_pairs(left);
         }
         if (cl == 1 && nleft == 1) {
-            total += 12.0 * H;
+            total += 10.0 * H;
             return;
         }
         if (cl >= 2 && nleft == 2) {
             total += 16.0 * H;
             return;
         }
-        if (cl == 3 && nleft == 4 && nleft <= mb) {
+        if (cl >= 3 && nleft == 4 && nleft <= mb) {
             // pair sums at both ends: four single-photon updates, then per
             // split {x, y} | {a, b}: the propagator of q + k_x + k_y, two vertex
             // halves and their sum, one propagator half and one pair closing
             for (int s = 0; s < n; ++s)
-                if (left >> s & 1u) total += 14.0 + 40.0 * var_count(used | (1u << s));
+                if (left >> s & 1u) total += 14.0 + 36.0 * var_count(used | (1u << s));
             for (int x = 0; x < n; ++x)
                 for (int y = x + 1; y < n; ++y)
                     if ((left >> x & 1u) && (left >> y & 1u))
-                        total += 14.0 + 64.0 * var_count(used | (1u << x) | (1u << y)) + 16.0 * H;
+                        total += 14.0 + 56.0 * var_count(used | (1u << x) | (1u << y)) + 16.0 * H;
             return;
         }
         for (int s = 0; s < n; ++s) {
             if (!(left >> s & 1u)) continue;
-            if (nleft > mb) total += 3.0 + 4.0 * H;  // top-level node builds its vertex block
+            if (nleft > mb) total += 4.0;  // top-level node builds its vertex block
             const unsigned u = used | (1u << s);
-            total += 14.0 + 40.0 * var_count(u);
+            total += 14.0 + 36.0 * var_count(u);
             below(u, mb);
         }
     }
@@ -1571,7 +1577,7 @@ heget_status heget_set_kernel_shape(int n, heget_prec prec, const heget_shape *s
     }
     const heget::Me2Variant *v =
         find_variant(prec, n, shape->unrolled, shape->helicities_per_walk, shape->closing,
-                     shape->waves_per_block, shape->prefetch);
+                     shape->waves_per_block, shape->prefetch, shape->waves_per_simd);
     if (!v) return fail(HEGET_ERR_ARG, "no compiled kernel shape with these parameters");
     g_tuned[prec][n] = v;
     return HEGET_OK;

@@ -13,12 +13,6 @@
 
 namespace heget {
 
-// The hardware estimate of 1/sqrt(x).  Used only for the vertex scale t,
-// whose rounding cancels exactly against the FP64 normalisation, so its
-// accuracy does not enter |M|^2.
-__device__ __forceinline__ float rsqrt_approx(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsqrt_approx(double x) { return __builtin_amdgcn_rsq(x); }
-
 // Inputs of one point of a work item, loaded ahead of the walk that uses them.
 template <int N>
 struct PointLoad {
@@ -82,9 +76,9 @@ __device__ __forceinline__ void me2_compute(const PointLoad<N> &q, int64_t npts,
     double norm = ((E1 + p1z) * sc) * (2.0 * E2 * sc);
 
     PointIn<R, N> in;
-    in.q0 = {static_cast<R>(-(E2 + p2z) * sc), static_cast<R>(-(E2 - p2z) * sc), R(0), R(0), R(0)};
-    in.p1 = {static_cast<R>((E1 + p1z) * sc), static_cast<R>((E1 - p1z) * sc), R(0), R(0), R(0)};
-    double norm_den = 1.0;  // product of the photons' 2 E^2 pT^2 t^2, divided out once
+    in.q0 = {static_cast<R>(-(E2 + p2z) * sc), static_cast<R>(-(E2 - p2z) * sc), R(0), R(0), R(0), R(0)};
+    in.p1 = {static_cast<R>((E1 + p1z) * sc), static_cast<R>((E1 - p1z) * sc), R(0), R(0), R(0), R(0)};
+    double norm_den = 1.0;  // product of the photons' 2 E^2 / pT^2, divided out once
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         const int r = 8 + 4 * j;
@@ -102,19 +96,26 @@ __device__ __forceinline__ void me2_compute(const PointLoad<N> &q, int64_t npts,
             small = pt2 / big;
         const R kp = kz >= 0.0 ? static_cast<R>(big) : small;
         const R km = kz >= 0.0 ? small : static_cast<R>(big);
-        // vertex normalisation t ~ 1/(sqrt(2) E pT), any rounding of it: the
-        // remainder (1/(sqrt(2) E pT t))^2 goes into the FP64 normalisation
-        const double e2pt2 = 2.0 * E * E * pt2;
-        const R t = rsqrt_approx(static_cast<R>(e2pt2));
-        const double td = static_cast<double>(t);
-        norm_den *= e2pt2 * td * td;
-        in.k[j] = {kp, km, static_cast<R>(kx), static_cast<R>(ky), t};
+        // 1/k+ and 1/k- for the normalised vertex block (hardware reciprocal
+        // in FP32, correctly rounded in FP64); the block's factor
+        // pT / (sqrt(2) E) per photon enters |M|^2 here, in FP64
+        R ip, im;
+        if constexpr (std::is_same<R, float>::value) {
+            ip = __builtin_amdgcn_rcpf(kp);
+            im = __builtin_amdgcn_rcpf(km);
+        } else {
+            ip = 1.0 / kp;
+            im = 1.0 / km;
+        }
+        norm_den *= 2.0 * E * E / pt2;
+        in.k[j] = {kp, km, static_cast<R>(kx), static_cast<R>(ky), ip, im};
         if constexpr (kTopInLds) {
             tab[0 * N * 64 + j * 64 + lane] = in.k[j].p;
             tab[1 * N * 64 + j * 64 + lane] = in.k[j].m;
             tab[2 * N * 64 + j * 64 + lane] = in.k[j].x;
             tab[3 * N * 64 + j * 64 + lane] = in.k[j].y;
-            tab[4 * N * 64 + j * 64 + lane] = in.k[j].t;
+            tab[4 * N * 64 + j * 64 + lane] = in.k[j].ip;
+            tab[5 * N * 64 + j * 64 + lane] = in.k[j].im;
         }
     }
 
@@ -164,8 +165,11 @@ __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t
 // index of the one after) before the walk of the current one, so the walk
 // hides the memory latency even at one wave per SIMD.  Item numbers are
 // wave-uniform (scalar registers), so the loop and its bounds are scalar.
-template <typename R, int N, int MB, int H, int CL, int WPB, int PF>
-__global__ void __launch_bounds__(WPB * 64)
+// WPE > 0 asks the compiler for at least WPE waves per SIMD (registers capped
+// at 512 / WPE): the SIMD issues FP32 instructions of two waves side by side,
+// which one wave alone cannot use.
+template <typename R, int N, int MB, int H, int CL, int WPB, int PF, int WPE>
+__global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict__ index,
            const uint16_t *__restrict__ hel, const int64_t *__restrict__ d_count, int64_t count,
            int nchunks, double coef, double *__restrict__ out, int64_t ld_out,
@@ -232,11 +236,11 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
     }
 }
 
-template <typename R, int N, int MB, int H, int CL, int WPB, int PF = 0>
+template <typename R, int N, int MB, int H, int CL, int WPB, int PF = 0, int WPE = 0>
 constexpr Me2Variant variant()
 {
-    return Me2Variant{std::is_same<R, float>::value ? 1 : 0, N, MB, H, CL, WPB, PF,
-                      reinterpret_cast<const void *>(&me2_kernel<R, N, MB, H, CL, WPB, PF>)};
+    return Me2Variant{std::is_same<R, float>::value ? 1 : 0, N, MB, H, CL, WPB, PF, WPE,
+                      reinterpret_cast<const void *>(&me2_kernel<R, N, MB, H, CL, WPB, PF, WPE>)};
 }
 
 }  // namespace heget

@@ -27,13 +27,19 @@
 //    and with light-cone components k+ = E + kz, k- = E - kz, kappa = kx + i ky,
 //        sqrt(2) E pT V(+1) = [[ k+k-, -k+ kappa ], [ k- conj(kappa), -k+k- ]]
 //        sqrt(2) E pT V(-1) = [[ -k+k-, -k- kappa ], [ k+ conj(kappa), k+k- ]].
-//    The tree builds V = t V' from the momentum and t ~ 1/(sqrt(2) E pT)
-//    rounded to the working precision; every diagram contains each photon
-//    once, so the exact factor (1/(sqrt(2) E pT t))^2 per photon is applied
-//    to |M|^2 in FP64 at the end and the rounding of t cancels.
+//    Divided by its diagonal entry +-k+k- = +-pT^2 the block is
+//        V'(+1) = [[ 1, -kappa / k- ], [  conj(kappa) / k+, -1 ]]
+//        V'(-1) = [[ 1,  kappa / k+ ], [ -conj(kappa) / k-, -1 ]],
+//    so V(lam) = +-(pT / (sqrt(2) E)) V'(lam).  Every diagram contains each
+//    photon once, so the factors are common to all orderings of one helicity
+//    configuration: their signs change no |M|^2, and the magnitudes
+//    pT^2 / (2 E^2) per photon are applied to |M|^2 in FP64 at the end.  The
+//    tree works with V' = [[1, beta'], [gamma', -1]], whose unit diagonal
+//    turns every vertex product into fused multiply-adds on the current.
 //  * The ubar spinor of oxxxx2 is (0, 0, -sqrt(2 E2), 0) and the u spinor of
 //    ixxxx1 is (0, sqrt(E1 + p1z), 0, 0); their sizes are pulled out too, so
-//    the chain starts at g = (1, 0) and closes with amp = gamma g2 - a3 g3.
+//    the chain starts at g = (1, 0) and closes with amp = gamma g2 - a3 g3
+//    (gamma' g2 - g3 with the normalised block).
 //  * Current update (fvoxx0, lower block): with q the momentum after adding k
 //    and d = -1/q^2,
 //        sl1 = a3 g2 + beta g3,     sl2 = gamma g2 - a3 g3,
@@ -72,11 +78,11 @@
 
 namespace heget {
 
-// Light-cone momentum: p = E + z, m = E - z, x, y; for photons t is the
-// vertex normalisation ~ 1/(sqrt(2) E pT) (unused for internal momenta).
+// Light-cone momentum: p = E + z, m = E - z, x, y; for photons also
+// ip = 1 / p and im = 1 / m (unused for internal momenta).
 template <typename R>
 struct LMom {
-    R p, m, x, y, t;
+    R p, m, x, y, ip, im;
 };
 
 // Chain currents (g2, g3) for H helicity variants.
@@ -85,10 +91,10 @@ struct Chain {
     R g2r[H], g2i[H], g3r[H], g3i[H];
 };
 
-// Vertex block V' = [[a3, beta], [gamma, -a3]] for H variants.
+// Normalised vertex block V' = [[1, beta], [gamma, -1]] for H variants.
 template <typename R, int H>
 struct Vert {
-    R a3[H], br[H], bi[H], gr[H], gi[H];
+    R br[H], bi[H], gr[H], gi[H];
 };
 
 template <int H>
@@ -102,11 +108,6 @@ struct Slots {
     Vert<R, H> v[NS];
 };
 
-// Pair-closing row vectors U_ab (a < b) for the slot photons, per variant.
-template <typename R, int H, int NS>
-struct PairTab {
-    R u1r[NS][NS][H], u1i[NS][NS][H], u2r[NS][NS][H], u2i[NS][NS][H];
-};
 
 // Unused placeholder when the walk closes photon by photon (CL = 1).
 struct NoPairs {};
@@ -117,18 +118,15 @@ template <typename R, int H>
 __device__ __forceinline__ Vert<R, H> make_vert(const LMom<R> &k, uint32_t cfg0, int j)
 {
     Vert<R, H> v;
-    const R tp = k.t * k.p, tm = k.t * k.m;
-    const R a3 = tp * k.m;  // t pT^2
+    const R xp = k.x * k.ip, yp = k.y * k.ip;  // kappa / k+
+    const R xm = k.x * k.im, ym = k.y * k.im;  // kappa / k-
 #pragma unroll
     for (int h = 0; h < H; ++h) {
         const bool plus = ((cfg0 + h) >> j) & 1u;
-        const R cb = plus ? tp : tm;  // coefficient of -kappa in beta
-        const R cg = plus ? tm : tp;  // coefficient of conj(kappa) in gamma
-        v.a3[h] = plus ? a3 : -a3;
-        v.br[h] = -cb * k.x;
-        v.bi[h] = -cb * k.y;
-        v.gr[h] = cg * k.x;
-        v.gi[h] = -cg * k.y;
+        v.br[h] = plus ? -xm : xp;
+        v.bi[h] = plus ? -ym : yp;
+        v.gr[h] = plus ? xp : -xm;
+        v.gi[h] = plus ? -yp : ym;
     }
     return v;
 }
@@ -158,7 +156,8 @@ __device__ __forceinline__ Prop<R> propagate(const LMom<R> &q, const LMom<R> &k,
     qn.m = q.m + k.m;
     qn.x = q.x + k.x;
     qn.y = q.y + k.y;
-    qn.t = R(0);
+    qn.ip = R(0);
+    qn.im = R(0);
     const R q2 = qn.p * qn.m - qn.x * qn.x - qn.y * qn.y;
     const R d = neg_recip(q2);
     return {d * qn.m, d * qn.p, d * qn.x, d * qn.y};
@@ -176,10 +175,10 @@ __device__ __forceinline__ Half<R, H> vertex_half(const Vert<R, H> &v, const Cha
     Half<R, H> s;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-        s.s1r[h] = v.a3[h] * c.g2r[h] + v.br[h] * c.g3r[h] - v.bi[h] * c.g3i[h];
-        s.s1i[h] = v.a3[h] * c.g2i[h] + v.br[h] * c.g3i[h] + v.bi[h] * c.g3r[h];
-        s.s2r[h] = v.gr[h] * c.g2r[h] - v.gi[h] * c.g2i[h] - v.a3[h] * c.g3r[h];
-        s.s2i[h] = v.gr[h] * c.g2i[h] + v.gi[h] * c.g2r[h] - v.a3[h] * c.g3i[h];
+        s.s1r[h] = fma(v.br[h], c.g3r[h], fma(-v.bi[h], c.g3i[h], c.g2r[h]));
+        s.s1i[h] = fma(v.br[h], c.g3i[h], fma(v.bi[h], c.g3r[h], c.g2i[h]));
+        s.s2r[h] = fma(v.gr[h], c.g2r[h], fma(-v.gi[h], c.g2i[h], -c.g3r[h]));
+        s.s2i[h] = fma(v.gr[h], c.g2i[h], fma(v.gi[h], c.g2r[h], -c.g3i[h]));
     }
     return s;
 }
@@ -191,10 +190,10 @@ __device__ __forceinline__ void vertex_half_add(const Vert<R, H> &v, const Chain
 {
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-        s.s1r[h] = fma(v.a3[h], c.g2r[h], fma(v.br[h], c.g3r[h], fma(-v.bi[h], c.g3i[h], s.s1r[h])));
-        s.s1i[h] = fma(v.a3[h], c.g2i[h], fma(v.br[h], c.g3i[h], fma(v.bi[h], c.g3r[h], s.s1i[h])));
-        s.s2r[h] = fma(v.gr[h], c.g2r[h], fma(-v.gi[h], c.g2i[h], fma(-v.a3[h], c.g3r[h], s.s2r[h])));
-        s.s2i[h] = fma(v.gr[h], c.g2i[h], fma(v.gi[h], c.g2r[h], fma(-v.a3[h], c.g3i[h], s.s2i[h])));
+        s.s1r[h] = fma(v.br[h], c.g3r[h], fma(-v.bi[h], c.g3i[h], s.s1r[h] + c.g2r[h]));
+        s.s1i[h] = fma(v.br[h], c.g3i[h], fma(v.bi[h], c.g3r[h], s.s1i[h] + c.g2i[h]));
+        s.s2r[h] = fma(v.gr[h], c.g2r[h], fma(-v.gi[h], c.g2i[h], s.s2r[h] - c.g3r[h]));
+        s.s2i[h] = fma(v.gr[h], c.g2i[h], fma(v.gi[h], c.g2r[h], s.s2i[h] - c.g3i[h]));
     }
 }
 
@@ -219,14 +218,14 @@ __device__ __forceinline__ void update(const Vert<R, H> &v, const Chain<R, H> &c
     propagator_half<R, H>(P, vertex_half<R, H>(v, c), o);
 }
 
-// Closing vertex (iovxx0 with the u spinor): amp = gamma g2 - a3 g3, summed in FP64.
+// Closing vertex (iovxx0 with the u spinor): amp = gamma g2 - g3, summed in FP64.
 template <typename R, int H>
 __device__ __forceinline__ void close_chain(const Vert<R, H> &v, const Chain<R, H> &c, Acc<H> &acc)
 {
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-        const R ar = v.gr[h] * c.g2r[h] - v.gi[h] * c.g2i[h] - v.a3[h] * c.g3r[h];
-        const R ai = v.gr[h] * c.g2i[h] + v.gi[h] * c.g2r[h] - v.a3[h] * c.g3i[h];
+        const R ar = fma(v.gr[h], c.g2r[h], fma(-v.gi[h], c.g2i[h], -c.g3r[h]));
+        const R ai = fma(v.gr[h], c.g2i[h], fma(v.gi[h], c.g2r[h], -c.g3i[h]));
         acc.re[h] += static_cast<double>(ar);
         acc.im[h] += static_cast<double>(ai);
     }
@@ -242,13 +241,17 @@ __device__ __forceinline__ void for_each_bit(F &&f)
     }
 }
 
-// Pair vectors of the slot photons: w_r = c_r d(q_r) P(q_r) with q_r = p1 - k_r,
-// u_jr = w_r V_j, U_jr = u_jr + u_rj.
+// The u-end currents of the slot photons: w_r = c_r d(q_r) P(q_r) with
+// q_r = p1 - k_r and c_r = (gamma_r, -1) (the current after photon r met the
+// u spinor).
 template <typename R, int H, int NS>
-__device__ __forceinline__ void make_pairs(const Slots<R, H, NS> &S, const LMom<R> &p1,
-                                           PairTab<R, H, NS> &T)
-{
+struct PairW {
     R w1r[NS][H], w1i[NS][H], w2r[NS][H], w2i[NS][H];
+};
+
+template <typename R, int H, int NS>
+__device__ __forceinline__ void make_w(const Slots<R, H, NS> &S, const LMom<R> &p1, PairW<R, H, NS> &W)
+{
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
         LMom<R> q;
@@ -261,52 +264,90 @@ __device__ __forceinline__ void make_pairs(const Slots<R, H, NS> &S, const LMom<
         const R Pm = d * q.m, Pp = d * q.p, Px = d * q.x, Py = d * q.y;
 #pragma unroll
         for (int h = 0; h < H; ++h) {
-            const R gr = S.v[r].gr[h], gi = S.v[r].gi[h], a3 = S.v[r].a3[h];
-            w1r[r][h] = gr * Pm + a3 * Px;
-            w1i[r][h] = gi * Pm - a3 * Py;
-            w2r[r][h] = -(gr * Px - gi * Py) - a3 * Pp;
-            w2i[r][h] = -(gr * Py + gi * Px);
+            const R gr = S.v[r].gr[h], gi = S.v[r].gi[h];
+            W.w1r[r][h] = fma(gr, Pm, Px);
+            W.w1i[r][h] = fma(gi, Pm, -Py);
+            W.w2r[r][h] = -(gr * Px - gi * Py) - Pp;
+            W.w2i[r][h] = -(gr * Py + gi * Px);
         }
     }
+}
+
+// The pair vector U_ab = u_ab + u_ba for helicity variant h, u_jr = w_r V_j.
+template <typename R, int H, int NS>
+__device__ __forceinline__ void pair_u(const Slots<R, H, NS> &S, const PairW<R, H, NS> &W, int a, int b,
+                                       int h, R &u1r, R &u1i, R &u2r, R &u2i)
+{
+    // u_ab = w_b V_a and u_ba = w_a V_b; V = [[1, beta], [gamma, -1]]
+    const Vert<R, H> &va = S.v[a], &vb = S.v[b];
+    const R x1r = fma(W.w2r[b][h], va.gr[h], fma(-W.w2i[b][h], va.gi[h], W.w1r[b][h]));
+    const R x1i = fma(W.w2r[b][h], va.gi[h], fma(W.w2i[b][h], va.gr[h], W.w1i[b][h]));
+    const R x2r = fma(W.w1r[b][h], va.br[h], fma(-W.w1i[b][h], va.bi[h], -W.w2r[b][h]));
+    const R x2i = fma(W.w1r[b][h], va.bi[h], fma(W.w1i[b][h], va.br[h], -W.w2i[b][h]));
+    // + u_ba, continued as fused multiply-adds on u_ab
+    u1r = fma(W.w2r[a][h], vb.gr[h], fma(-W.w2i[a][h], vb.gi[h], x1r + W.w1r[a][h]));
+    u1i = fma(W.w2r[a][h], vb.gi[h], fma(W.w2i[a][h], vb.gr[h], x1i + W.w1i[a][h]));
+    u2r = fma(W.w1r[a][h], vb.br[h], fma(-W.w1i[a][h], vb.bi[h], x2r - W.w2r[a][h]));
+    u2i = fma(W.w1r[a][h], vb.bi[h], fma(W.w1i[a][h], vb.br[h], x2i - W.w2i[a][h]));
+}
+
+// Table of every pair vector, built once per subtree entry.
+template <typename R, int H, int NS>
+struct PairTab {
+    R u1r[NS][NS][H], u1i[NS][NS][H], u2r[NS][NS][H], u2i[NS][NS][H];
+    __device__ __forceinline__ void get(int a, int b, int h, R &x1r, R &x1i, R &x2r, R &x2i) const
+    {
+        x1r = u1r[a][b][h];
+        x1i = u1i[a][b][h];
+        x2r = u2r[a][b][h];
+        x2i = u2i[a][b][h];
+    }
+};
+
+template <typename R, int H, int NS>
+__device__ __forceinline__ void make_pairs(const Slots<R, H, NS> &S, const PairW<R, H, NS> &W,
+                                           PairTab<R, H, NS> &T)
+{
 #pragma unroll
     for (int a = 0; a < NS; ++a)
 #pragma unroll
         for (int b = a + 1; b < NS; ++b)
 #pragma unroll
-            for (int h = 0; h < H; ++h) {
-                // u_ab = w_b V_a and u_ba = w_a V_b; V = [[a3, beta], [gamma, -a3]]
-                const Vert<R, H> &va = S.v[a], &vb = S.v[b];
-                const R x1r = w1r[b][h] * va.a3[h] + w2r[b][h] * va.gr[h] - w2i[b][h] * va.gi[h];
-                const R x1i = w1i[b][h] * va.a3[h] + w2r[b][h] * va.gi[h] + w2i[b][h] * va.gr[h];
-                const R x2r = w1r[b][h] * va.br[h] - w1i[b][h] * va.bi[h] - w2r[b][h] * va.a3[h];
-                const R x2i = w1r[b][h] * va.bi[h] + w1i[b][h] * va.br[h] - w2i[b][h] * va.a3[h];
-                // + u_ba, continued as fused multiply-adds on u_ab
-                T.u1r[a][b][h] = fma(w1r[a][h], vb.a3[h], fma(w2r[a][h], vb.gr[h], fma(-w2i[a][h], vb.gi[h], x1r)));
-                T.u1i[a][b][h] = fma(w1i[a][h], vb.a3[h], fma(w2r[a][h], vb.gi[h], fma(w2i[a][h], vb.gr[h], x1i)));
-                T.u2r[a][b][h] = fma(w1r[a][h], vb.br[h], fma(-w1i[a][h], vb.bi[h], fma(-w2r[a][h], vb.a3[h], x2r)));
-                T.u2i[a][b][h] = fma(w1r[a][h], vb.bi[h], fma(w1i[a][h], vb.br[h], fma(-w2i[a][h], vb.a3[h], x2i)));
-            }
+            for (int h = 0; h < H; ++h)
+                pair_u<R, H, NS>(S, W, a, b, h, T.u1r[a][b][h], T.u1i[a][b][h], T.u2r[a][b][h],
+                                 T.u2i[a][b][h]);
 }
 
-// Close a node with slots a < b left: amp = U_ab . g, summed in FP64.
+// Pair vectors formed where they are used (a subtree whose every pair is
+// closed once, as the four-photon subtree is).
 template <typename R, int H, int NS>
-__device__ __forceinline__ void close_pair(const PairTab<R, H, NS> &T, int a, int b,
-                                           const Chain<R, H> &c, Acc<H> &acc)
+struct PairLazy {
+    const Slots<R, H, NS> &S;
+    const PairW<R, H, NS> &W;
+    __device__ __forceinline__ void get(int a, int b, int h, R &x1r, R &x1i, R &x2r, R &x2i) const
+    {
+        pair_u<R, H, NS>(S, W, a, b, h, x1r, x1i, x2r, x2i);
+    }
+};
+
+// Close a node with slots a < b left: amp = U_ab . g, summed in FP64.
+template <typename R, int H, typename PT>
+__device__ __forceinline__ void close_pair(const PT &T, int a, int b, const Chain<R, H> &c, Acc<H> &acc)
 {
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-        const R ar = T.u1r[a][b][h] * c.g2r[h] - T.u1i[a][b][h] * c.g2i[h] +
-                     T.u2r[a][b][h] * c.g3r[h] - T.u2i[a][b][h] * c.g3i[h];
-        const R ai = T.u1r[a][b][h] * c.g2i[h] + T.u1i[a][b][h] * c.g2r[h] +
-                     T.u2r[a][b][h] * c.g3i[h] + T.u2i[a][b][h] * c.g3r[h];
+        R u1r, u1i, u2r, u2i;
+        T.get(a, b, h, u1r, u1i, u2r, u2i);
+        const R ar = u1r * c.g2r[h] - u1i * c.g2i[h] + u2r * c.g3r[h] - u2i * c.g3i[h];
+        const R ai = u1r * c.g2i[h] + u1i * c.g2r[h] + u2r * c.g3i[h] + u2i * c.g3r[h];
         acc.re[h] += static_cast<double>(ar);
         acc.im[h] += static_cast<double>(ai);
     }
 }
 
-template <typename R, int H, int NS>
-__device__ __forceinline__ void close_pair_wide(const PairTab<R, H, NS> &T, int a, int b,
-                                                const Chain<R, H> &c, Acc<H> &acc);
+template <typename R, int H, typename PT>
+__device__ __forceinline__ void close_pair_wide(const PT &T, int a, int b, const Chain<R, H> &c,
+                                                Acc<H> &acc);
 
 // The last four photons of every ordering below a node (slots in MASK,
 // four of them) with pair sums at both ends (CL = 3).  The 24 orderings
@@ -316,7 +357,9 @@ __device__ __forceinline__ void close_pair_wide(const PairTab<R, H, NS> &T, int 
 // same momentum q + k_x + k_y, so they share their propagator:
 //     G_xy = d P(q + k_x + k_y) [V_y g_x + V_x g_y],  g_x = current after x,
 // and the node closes with six products U_ab . G_xy instead of twelve.
-template <typename R, int H, int NS, unsigned MASK, typename PT>
+// CL = 3 takes each split's product in FP64 where H >= 8 (close_pair_wide);
+// CL = 4 always in the working precision, converted once into the FP64 sum.
+template <typename R, int H, int NS, int CL, unsigned MASK, typename PT>
 __device__ __forceinline__ void quad_close(const Slots<R, H, NS> &S, const PT &T, const Chain<R, H> &c,
                                            const LMom<R> &q, Acc<H> &acc)
 {
@@ -346,11 +389,12 @@ __device__ __forceinline__ void quad_close(const Slots<R, H, NS> &S, const PT &T
         Chain<R, H> g2;
         propagator_half<R, H>(P, s, g2);
         // FP64 products pay off where a split's conversions are shared by
-        // many configurations (and always in FP64, where there are none)
-        if constexpr (std::is_same<R, double>::value || H >= 8)
-            close_pair_wide<R, H, NS>(T, sl[A[t]], sl[B[t]], g2, acc);
+        // many configurations and FP64 issues as fast as FP32 (and always in
+        // FP64, where there are none)
+        if constexpr (std::is_same<R, double>::value || (H >= 8 && CL == 3))
+            close_pair_wide<R, H>(T, sl[A[t]], sl[B[t]], g2, acc);
         else
-            close_pair<R, H, NS>(T, sl[A[t]], sl[B[t]], g2, acc);
+            close_pair<R, H>(T, sl[A[t]], sl[B[t]], g2, acc);
     }
 }
 
@@ -361,14 +405,15 @@ __device__ __forceinline__ void quad_close(const Slots<R, H, NS> &S, const PT &T
 // conversions of the four pair vectors and four currents of a split are
 // shared by up to sixteen helicity configurations, which makes this cheaper
 // than an FP32 product followed by a conversion and an FP64 add.
-template <typename R, int H, int NS>
-__device__ __forceinline__ void close_pair_wide(const PairTab<R, H, NS> &T, int a, int b,
-                                                const Chain<R, H> &c, Acc<H> &acc)
+template <typename R, int H, typename PT>
+__device__ __forceinline__ void close_pair_wide(const PT &T, int a, int b, const Chain<R, H> &c,
+                                                Acc<H> &acc)
 {
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-        const double u1r = T.u1r[a][b][h], u1i = T.u1i[a][b][h];
-        const double u2r = T.u2r[a][b][h], u2i = T.u2i[a][b][h];
+        R x1r, x1i, x2r, x2i;
+        T.get(a, b, h, x1r, x1i, x2r, x2i);
+        const double u1r = x1r, u1i = x1i, u2r = x2r, u2i = x2i;
         const double g2r = c.g2r[h], g2i = c.g2i[h], g3r = c.g3r[h], g3i = c.g3i[h];
         acc.re[h] = fma(u1r, g2r, fma(-u1i, g2i, fma(u2r, g3r, fma(-u2i, g3i, acc.re[h]))));
         acc.im[h] = fma(u1r, g2i, fma(u1i, g2r, fma(u2r, g3i, fma(u2i, g3r, acc.im[h]))));
@@ -377,19 +422,19 @@ __device__ __forceinline__ void close_pair_wide(const PairTab<R, H, NS> &T, int 
 
 // Unrolled subtree over the slot photons in MASK, entered with current c at
 // momentum q.  CL = 1 closes photon by photon; CL = 2 closes the last pair;
-// CL = 3 closes the last four photons with pair sums at both ends.
+// CL = 3 and 4 close the last four photons with pair sums at both ends.
 template <typename R, int H, int NS, int CL, unsigned MASK, typename PT>
 __device__ __forceinline__ void subtree(const Slots<R, H, NS> &S, const PT &T, const Chain<R, H> &c,
                                         const LMom<R> &q, Acc<H> &acc)
 {
     if constexpr (CL == 1 && __builtin_popcount(MASK) == 1) {
         close_chain<R, H>(S.v[__builtin_ctz(MASK)], c, acc);
-    } else if constexpr (CL == 3 && __builtin_popcount(MASK) == 4) {
-        quad_close<R, H, NS, MASK>(S, T, c, q, acc);
+    } else if constexpr (CL >= 3 && __builtin_popcount(MASK) == 4) {
+        quad_close<R, H, NS, CL, MASK>(S, T, c, q, acc);
     } else if constexpr (CL >= 2 && __builtin_popcount(MASK) == 2) {
         constexpr int a = __builtin_ctz(MASK);
         constexpr int b = __builtin_ctz(MASK & (MASK - 1u));
-        close_pair<R, H, NS>(T, a, b, c, acc);
+        close_pair<R, H>(T, a, b, c, acc);
     } else {
         for_each_bit<MASK>([&](auto bit) {
             constexpr int s = decltype(bit)::value;
@@ -402,28 +447,37 @@ __device__ __forceinline__ void subtree(const Slots<R, H, NS> &S, const PT &T, c
     }
 }
 
-// Enter a subtree over all NS slots (builds the pair vectors first for CL >= 2).
+// Enter a subtree over all NS slots (forms the u-end currents first for CL >= 2).
 template <typename R, int H, int NS, int CL>
 __device__ __forceinline__ void run_subtree(const Slots<R, H, NS> &S, const LMom<R> &p1,
                                             const Chain<R, H> &c, const LMom<R> &q, Acc<H> &acc)
 {
     if constexpr (CL >= 2) {
-        PairTab<R, H, NS> T;
-        make_pairs<R, H, NS>(S, p1, T);
-        subtree<R, H, NS, CL, (1u << NS) - 1u>(S, T, c, q, acc);
+        PairW<R, H, NS> W;
+        make_w<R, H, NS>(S, p1, W);
+        if constexpr (NS == 4 && CL >= 3) {
+            // every pair of a four-photon subtree closes exactly once: form
+            // each pair vector where it is used instead of holding the table
+            const PairLazy<R, H, NS> T{S, W};
+            subtree<R, H, NS, CL, (1u << NS) - 1u>(S, T, c, q, acc);
+        } else {
+            PairTab<R, H, NS> T;
+            make_pairs<R, H, NS>(S, W, T);
+            subtree<R, H, NS, CL, (1u << NS) - 1u>(S, T, c, q, acc);
+        }
     } else {
         subtree<R, H, NS, CL, (1u << NS) - 1u>(S, NoPairs{}, c, q, acc);
     }
 }
 
-// LDS photon table of one wave: [field 0..4][photon][lane] = (k+, k-, kx, ky, t).
-constexpr int kPhotonFields = 5;
+// LDS photon table of one wave: [field 0..5][photon][lane] = (k+, k-, kx, ky, 1/k+, 1/k-).
+constexpr int kPhotonFields = 6;
 
 template <typename R, int N>
 __device__ __forceinline__ LMom<R> lds_photon(const R *tab, int j, int lane)
 {
     const R *b = tab + j * 64 + lane;
-    return {b[0], b[N * 64], b[2 * N * 64], b[3 * N * 64], b[4 * N * 64]};
+    return {b[0], b[N * 64], b[2 * N * 64], b[3 * N * 64], b[4 * N * 64], b[5 * N * 64]};
 }
 
 // Wave-uniform walk of the top n-MB levels.  `rem` = photons not yet used.

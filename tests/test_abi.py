@@ -123,30 +123,32 @@ def test_helas_record_sizes_and_host_checks():
 
 def _flops_unshared(n, mb, h, cl):
     """Closed form of the algorithmic count when no value is shared between the
-    walk's helicities: every node, closing, vertex block and pair vector h times."""
+    walk's helicities: every node, closing and pair vector h times (vertex
+    blocks with a unit diagonal: a node update is 14 + 36 per helicity)."""
     import math
     f = math.factorial
     ns = min(n, mb)
-    if cl == 3 and ns < 4:  # no four-photon subtree: closes as pairs
+    if cl >= 3 and ns < 4:  # no four-photon subtree: closes as pairs
         cl = 2
     nodes = sum(f(n) // f(n - j) for j in range(1, n - cl + 1))
     subtrees = f(n) // f(ns)
     top = sum(f(n) // f(n - j) for j in range(1, n - ns + 1))
-    walk = nodes * (14 + 40 * h) + (ns * subtrees + top) * (3 + 4 * h) + 4 * h
-    if cl == 3 and ns >= 4:
+    walk = nodes * (14 + 36 * h) + (ns * subtrees + top) * 4 + 4 * h
+    pairs = subtrees * (ns * (12 + 11 * h) + ns * (ns - 1) * 16 * h + ns * (ns - 1) // 2 * 4 * h)
+    if cl >= 3 and ns >= 4:
         # the last four photons of every ordering: n!/4! nodes, each with four
         # single-photon updates and six splits (propagator, two vertex halves
         # and their sum, propagator half, pair closing)
         quads = f(n) // f(4)
         nodes = sum(f(n) // f(n - j) for j in range(1, n - 4 + 1))
-        walk = nodes * (14 + 40 * h) + (ns * subtrees + top) * (3 + 4 * h) + 4 * h
-        walk += quads * (4 * (14 + 40 * h) + 6 * (14 + 64 * h + 16 * h))
-        walk += subtrees * (ns * (12 + 14 * h) + ns * (ns - 1) * 20 * h + ns * (ns - 1) // 2 * 4 * h)
+        walk = nodes * (14 + 36 * h) + (ns * subtrees + top) * 4 + 4 * h
+        walk += quads * (4 * (14 + 36 * h) + 6 * (14 + 56 * h + 16 * h))
+        walk += pairs
     elif cl == 1:
-        walk += f(n) * 12 * h
+        walk += f(n) * 10 * h
     else:
         walk += f(n) // 2 * 16 * h
-        walk += subtrees * (ns * (12 + 14 * h) + ns * (ns - 1) * 20 * h + ns * (ns - 1) // 2 * 4 * h)
+        walk += pairs
     return walk * 2 ** n // h
 
 
@@ -161,7 +163,7 @@ def test_flop_count_of_every_shape():
                     H.set_kernel_shape(n, prec, shape)
                     f, got = H.me2_flops(n, prec)
                     assert got == shape
-                    mb, h, cl, wpb, pf = shape
+                    mb, h, cl, wpb, pf, wpe = shape
                     ref = _flops_unshared(n, mb, h, cl)
                     if h == 1 or n > mb:
                         assert f == ref, (n, shape, f, ref)
