@@ -70,9 +70,10 @@ def run_steps(H, torch, n, cfg, steps, warmup, nstreams=1):
     each writes its result record into its own slot of a device buffer (no
     host callback).  The step time is taken without per-kernel events (an
     event record stalls the stream by a few microseconds); the amplitude kernel
-    is then timed over as many further passes, on one stream, with HIP events
-    on the launch stream."""
-    total = warmup + 2 * steps
+    is then timed over at least 200 further passes, on one stream, with HIP
+    events on the launch stream."""
+    kreps = max(steps, 200)
+    total = warmup + steps + kreps
     buf = torch.zeros((total, 64), dtype=torch.uint8, device="cuda")
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(nstreams - 1)]
     # every stream's first pass sizes its scratch set: keep that out of the timing

@@ -21,6 +21,25 @@ struct Vec4 {
     double e, x, y, z;
 };
 
+// sqrt(x) for positive normal x (every square root of the generator: the
+// arguments are bounded away from zero, overflow and denormals): the
+// hardware estimate of 1/sqrt(x), one Goldschmidt step for the root and its
+// half-reciprocal, then two Newton corrections of the root, which leave it
+// within an ulp.  Without the range scaling and special cases of the
+// general square root, it issues half the instructions.
+__device__ __forceinline__ double sqrt_pos(double x)
+{
+    const double r = __builtin_amdgcn_rsq(x);
+    double g = x * r, h = 0.5 * r;
+    const double e = fma(-h, g, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+
 // RAMBO's conformal transformation in place: boost the N vectors to the rest
 // frame of their sum Q and rescale the sum to (sqrt_s, 0, 0, 0).  1/M and
 // 1/(1 + gamma) = M/(M + Q0) both come from the one quotient 1/(M (M + Q0)).
@@ -35,7 +54,7 @@ __device__ __forceinline__ void conformal_map(double sqrt_s, Vec4 (&k)[N])
         Qy += k[i].y;
         Qz += k[i].z;
     }
-    const double M = sqrt(Qe * Qe - Qx * Qx - Qy * Qy - Qz * Qz);
+    const double M = sqrt_pos(Qe * Qe - Qx * Qx - Qy * Qy - Qz * Qz);
     const double r = 1.0 / (M * (M + Qe));
     const double inv_m = (M + Qe) * r;
     const double bx = -Qx * inv_m, by = -Qy * inv_m, bz = -Qz * inv_m;
@@ -91,7 +110,7 @@ __device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t poi
         uniform_quad(seed, point, static_cast<uint32_t>(i), 0u, u);
         const double ucos = u[0], uphi = u[1], ue1 = u[2], ue2 = u[3];
         const double c = 2.0 * ucos - 1.0;
-        const double s = sqrt(1.0 - c * c);
+        const double s = sqrt_pos(1.0 - c * c);
         double sf, cf;
         fm::sincospi(2.0 * uphi, &sf, &cf);  // azimuth 2 pi uphi
         const double e = -fm::log(ue1 * ue2);
@@ -104,7 +123,7 @@ __device__ __forceinline__ void rambo(double sqrt_s, uint64_t seed, uint64_t poi
     // now a near-identity, so the result is massless and conserves momentum to
     // rounding (exact arithmetic gives the same points).
 #pragma unroll
-    for (int i = 0; i < N; ++i) k[i].e = sqrt(k[i].x * k[i].x + k[i].y * k[i].y + k[i].z * k[i].z);
+    for (int i = 0; i < N; ++i) k[i].e = sqrt_pos(k[i].x * k[i].x + k[i].y * k[i].y + k[i].z * k[i].z);
     rebalance<N>(sqrt_s, k);
 }
 
