@@ -16,20 +16,25 @@
 
 namespace heget {
 
-// Kinematics, cut decision and weight of one point in mode MODE.
+// Kinematics and weight of one point in mode MODE, with the cut decision
+// split: the FP32 screen only, giving 1 (pass),
+// 0 (fail) or -1 (undecided: a cut variable within the screen band of its
+// bound), and the frame rapidity for the FP64 decision of undecided points.
 template <int N, int MODE>
-__device__ __forceinline__ void point_setup(const GenParams &g, uint64_t point, Vec4 (&k)[N],
-                                            double &e_beam, double &w, bool &acc)
+__device__ __forceinline__ int point_setup_screened(const GenParams &g, uint64_t point, Vec4 (&k)[N],
+                                                    double &e_beam, double &w, double &y)
 {
     const PointKin pk = point_kinematics<MODE>(g, point);
     rambo<N>(pk.sqrt_shat, g.seed, point, k);
-    acc = pk.above && pass_cuts<N>(k, pk.y, g.pt_min, g.eta_max, g.dr_min);
+    const int s = pk.above ? screen_cuts<N>(k, pk.y, g.pt_min, g.eta_max, g.dr_min) : 0;
+    y = pk.y;
     e_beam = 0.5 * pk.sqrt_shat;
     const double shat = pk.sqrt_shat * pk.sqrt_shat;
     if (g.weight_kind == 0)
         w = g.phase_volume_coef * ipow(shat, N - 2);
     else
         w = g.partonic_coef * ipow(shat, N - 3) * pk.fpdf;
+    return s;
 }
 
 // SoA rows of one point: quark momenta (E, 0, 0, +-E), then the photons.
@@ -65,10 +70,29 @@ gen_kernel(GenParams g, double *__restrict__ mom, int64_t ld, double *__restrict
     if (g.clear_word && i == 0) *g.clear_word = 0u;
     bool acc = false;
     if (i < g.npoints) {
-        Vec4 k[N];
-        double e, w;
-        point_setup<N, MODE>(g, static_cast<uint64_t>(g.first + i), k, e, w, acc);
-        store_point<N>(mom, ld, i, e, k);
+        double w, y;
+        int s;
+        {
+            Vec4 k[N];
+            double e;
+            s = point_setup_screened<N, MODE>(g, static_cast<uint64_t>(g.first + i), k, e, w, y);
+            store_point<N>(mom, ld, i, e, k);
+        }
+        if (s < 0) {
+            // Rare: decide in FP64 from the momenta just stored.  The row
+            // pointer is passed through an empty asm statement so that the
+            // compiler reloads them instead of keeping every momentum live
+            // through the whole kernel (which costs two waves per SIMD).
+            __threadfence_block();  // this thread's stores above are visible to its loads
+            const double *m = mom + i;
+            asm volatile("" : "+v"(m));
+            Vec4 k[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                k[j] = {m[(8 + 4 * j) * ld], m[(9 + 4 * j) * ld], m[(10 + 4 * j) * ld], m[(11 + 4 * j) * ld]};
+            s = pass_cuts_fp64<N>(k, y, g.pt_min, g.eta_max, g.dr_min) ? 1 : 0;
+        }
+        acc = s == 1;
         wout[i] = acc ? w : 0.0;
         if (flag) flag[i] = acc ? 1 : 0;
         if (g.hel_out) g.hel_out[i] = draw_helicity<N>(g.seed, static_cast<uint64_t>(g.first + i));
