@@ -276,9 +276,14 @@ heget_status heget_timing_read(double *me2_ms, int64_t *me2_launches, int reset)
  *   waves_per_simd       0: registers as the compiler likes; k > 0: at most
  *                        512 / k registers per lane so that k waves share each
  *                        SIMD (its FP32 instructions then issue from two waves
- *                        at once) */
+ *                        at once)
+ *   points_per_lane      points each lane evaluates per work item (1, or 2
+ *                        with prefetch 0): a work item is that many 64-point
+ *                        tiles whose walks run as independent instruction
+ *                        streams */
 typedef struct {
-    int32_t unrolled, helicities_per_walk, closing, waves_per_block, prefetch, waves_per_simd;
+    int32_t unrolled, helicities_per_walk, closing, waves_per_block, prefetch, waves_per_simd,
+        points_per_lane;
 } heget_shape;
 
 /* Algorithmic floating-point operations per point of the amplitude kernel

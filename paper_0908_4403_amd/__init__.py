@@ -66,11 +66,11 @@ class _Config(C.Structure):
 class Shape(C.Structure):
     _fields_ = [("unrolled", C.c_int32), ("helicities_per_walk", C.c_int32),
                 ("closing", C.c_int32), ("waves_per_block", C.c_int32), ("prefetch", C.c_int32),
-                ("waves_per_simd", C.c_int32)]
+                ("waves_per_simd", C.c_int32), ("points_per_lane", C.c_int32)]
 
     def as_tuple(self):
         return (self.unrolled, self.helicities_per_walk, self.closing, self.waves_per_block,
-                self.prefetch, self.waves_per_simd)
+                self.prefetch, self.waves_per_simd, self.points_per_lane)
 
 
 class Result(C.Structure):
@@ -375,7 +375,7 @@ def timing_read(reset: bool = True):
 
 
 SHAPE_FIELDS = ("unrolled", "helicities_per_walk", "closing", "waves_per_block", "prefetch",
-                "waves_per_simd")
+                "waves_per_simd", "points_per_lane")
 
 
 def me2_flops(n: int, prec: int = FP32):

@@ -305,25 +305,26 @@ const heget::Me2Variant *pick_variant(int prec, int n)
     return heget::me2_default(prec, n);
 }
 
-const heget::Me2Variant *find_variant(int prec, int n, int mb, int h, int cl, int wpb, int pf, int wpe)
+const heget::Me2Variant *find_variant(int prec, int n, int mb, int h, int cl, int wpb, int pf, int wpe,
+                                      int ppl)
 {
     int cnt = 0;
     const heget::Me2Variant *v = heget::me2_variants(&cnt);
     for (int i = 0; i < cnt; ++i)
         if (v[i].prec == prec && v[i].n == n && v[i].mb == mb && v[i].h == h && v[i].cl == cl &&
-            v[i].wpb == wpb && v[i].pf == pf && v[i].wpe == wpe)
+            v[i].wpb == wpb && v[i].pf == pf && v[i].wpe == wpe && v[i].ppl == ppl)
             return &v[i];
     return nullptr;
 }
 
 heget_shape shape_of(const heget::Me2Variant &v)
 {
-    return heget_shape{v.mb, v.h, v.cl, v.wpb, v.pf, v.wpe};
+    return heget_shape{v.mb, v.h, v.cl, v.wpb, v.pf, v.wpe, v.ppl};
 }
 
 // Tuning cache: one JSON object per line,
 // {"arch": "gfx950", "prec": 1, "n": 4, "mb": 4, "h": 2, "cl": 2, "wpb": 4, "pf": 0, "wpe": 2,
-//  "ms": 0.48, "points": 1048576}
+//  "ppl": 1, "ms": 0.48, "points": 1048576}
 void load_tuning_cache()
 {
     const char *path = std::getenv("HEGET_TUNING_CACHE");
@@ -333,11 +334,11 @@ void load_tuning_cache()
     char line[512];
     while (std::fgets(line, sizeof line, f)) {
         char arch[64] = {0};
-        int prec, n, mb, h, cl, wpb, pf, wpe;
-        if (std::sscanf(line, " {\"arch\": \"%63[^\"]\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d, \"wpe\": %d",
-                        arch, &prec, &n, &mb, &h, &cl, &wpb, &pf, &wpe) == 9 &&
+        int prec, n, mb, h, cl, wpb, pf, wpe, ppl;
+        if (std::sscanf(line, " {\"arch\": \"%63[^\"]\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d, \"wpe\": %d, \"ppl\": %d",
+                        arch, &prec, &n, &mb, &h, &cl, &wpb, &pf, &wpe, &ppl) == 10 &&
             g_arch == arch && prec >= 0 && prec < 2 && n >= 2 && n <= 8) {
-            const heget::Me2Variant *v = find_variant(prec, n, mb, h, cl, wpb, pf, wpe);
+            const heget::Me2Variant *v = find_variant(prec, n, mb, h, cl, wpb, pf, wpe, ppl);
             if (v) g_tuned[prec][n] = v;
         }
     }
@@ -360,8 +361,9 @@ void save_tuning_cache(const heget::Me2Variant &v, double ms, int64_t points)
     }
     if (FILE *f = std::fopen(path, "w")) {
         for (const std::string &l : keep) std::fputs(l.c_str(), f);
-        std::fprintf(f, "{\"arch\": \"%s\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d, \"wpe\": %d, \"ms\": %.6f, \"points\": %lld}\n",
-                     g_arch.c_str(), v.prec, v.n, v.mb, v.h, v.cl, v.wpb, v.pf, v.wpe, ms, static_cast<long long>(points));
+        std::fprintf(f, "{\"arch\": \"%s\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d, \"wpe\": %d, \"ppl\": %d, \"ms\": %.6f, \"points\": %lld}\n",
+                     g_arch.c_str(), v.prec, v.n, v.mb, v.h, v.cl, v.wpb, v.pf, v.wpe, v.ppl, ms,
+                     static_cast<long long>(points));
         std::fclose(f);
     }
 }
@@ -713,7 +715,8 @@ heget_status xsec_enqueue(int n, const heget_config *cfg, heget_result *out, heg
     }
     b.part = nullptr;
     if (b.nchunks > 1) HG_TRY(scratch_t<double>(S_PART, size_t(b.nchunks) * size_t(np), &b.part));
-    HG_TRY(scratch_t<double>(S_PARTIALS, size_t(3) * size_t((np + 63) / 64), &b.partials));
+    // one spare tile slot: two-points-per-lane shapes write a zero sum there
+    HG_TRY(scratch_t<double>(S_PARTIALS, size_t(3) * size_t((np + 63) / 64 + 1), &b.partials));
     HG_TRY(scratch_t<double>(S_RES, 8, &b.res));
     HG_TRY(scratch_t<unsigned>(S_FLAGS, 1, &flags));
 
@@ -806,7 +809,7 @@ void carve_batch(Arena &ar, int ncfg, const int *n, const heget_config *cfgs, in
         // the persistent kernel always writes |M|^2 per chunk
         const bool need_part = b.nchunks > 1 || schedule == 1;
         b.part = need_part ? ar.take<double>(size_t(b.nchunks) * size_t(np)) : nullptr;
-        b.partials = ar.take<double>(size_t(3) * size_t((np + 63) / 64));
+        b.partials = ar.take<double>(size_t(3) * size_t((np + 63) / 64 + 1));  // + spare tile slot
         b.res = ar.take<double>(4);
     }
 }
@@ -988,7 +991,7 @@ void carve_static(int n, const heget_config &c, const heget::Me2Variant &v, Aren
     b.hel = sampled ? ar.take<uint16_t>(size_t(np)) : nullptr;
     b.wout = nullptr;
     b.part = b.nchunks > 1 ? ar.take<double>(size_t(b.nchunks) * size_t(np)) : nullptr;
-    b.partials = ar.take<double>(size_t(3) * size_t((np + 63) / 64));
+    b.partials = ar.take<double>(size_t(3) * size_t((np + 63) / 64 + 1));  // + spare tile slot
 }
 
 }  // namespace
@@ -1577,7 +1580,8 @@ heget_status heget_set_kernel_shape(int n, heget_prec prec, const heget_shape *s
     }
     const heget::Me2Variant *v =
         find_variant(prec, n, shape->unrolled, shape->helicities_per_walk, shape->closing,
-                     shape->waves_per_block, shape->prefetch, shape->waves_per_simd);
+                     shape->waves_per_block, shape->prefetch, shape->waves_per_simd,
+                     shape->points_per_lane);
     if (!v) return fail(HEGET_ERR_ARG, "no compiled kernel shape with these parameters");
     g_tuned[prec][n] = v;
     return HEGET_OK;

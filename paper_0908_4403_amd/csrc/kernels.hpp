@@ -20,6 +20,7 @@ struct Me2Variant {
     int wpb;    // waves per block
     int pf;     // 1: resident waves loop over the items, loading the next one ahead
     int wpe;    // minimum waves per SIMD the kernel is compiled for (0: no bound)
+    int ppl;    // points per lane: 64-point tiles per work item (1 unless pf = 0)
     const void *func;  // kernel symbol
 };
 

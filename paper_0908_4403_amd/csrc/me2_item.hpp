@@ -167,8 +167,12 @@ __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t
 // wave-uniform (scalar registers), so the loop and its bounds are scalar.
 // WPE > 0 asks the compiler for at least WPE waves per SIMD (registers capped
 // at 512 / WPE): the SIMD issues FP32 instructions of two waves side by side,
-// which one wave alone cannot use.
-template <typename R, int N, int MB, int H, int CL, int WPB, int PF, int WPE>
+// which one wave alone cannot use.  PPL = 2 (with PF = 0) gives each lane two
+// points: a work item is two consecutive 64-point tiles whose walks are
+// independent instruction streams in one loop body (each with its own LDS
+// photon table), for more instruction-level parallelism per wave; the
+// weighted partial-sum buffer needs one spare tile slot after the last tile.
+template <typename R, int N, int MB, int H, int CL, int WPB, int PF, int WPE, int PPL>
 __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict__ index,
            const uint16_t *__restrict__ hel, const int64_t *__restrict__ d_count, int64_t count,
@@ -176,11 +180,14 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
            const double *__restrict__ wfac, double *__restrict__ partials,
            double *__restrict__ wout, unsigned *__restrict__ flags)
 {
-    __shared__ R tab_all[N > MB ? WPB * kPhotonFields * N * 64 : 1];
+    static_assert(PPL == 1 || PF == 0, "several points per lane only without prefetch");
+    constexpr int kTab = N > MB ? kPhotonFields * N * 64 : 0;  // LDS photon table of one walk
+    __shared__ R tab_all[N > MB ? WPB * PPL * kTab : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t npts = d_count ? *d_count : count;
-    const int64_t nitems = ((npts + 63) >> 6) * nchunks;
+    const int64_t ntiles = (npts + 63) >> 6;
+    const int64_t nitems = ((ntiles + PPL - 1) / PPL) * nchunks;
     int64_t stride = static_cast<int64_t>(gridDim.x) * WPB;
     int64_t item = static_cast<int64_t>(blockIdx.x) * WPB + wave;
     int64_t end = nitems;
@@ -198,17 +205,34 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
         end = (x + 1) * per < nitems ? (x + 1) * per : nitems;
     }
     if (item >= end) return;  // whole wave
-    R *tab = tab_all + (N > MB ? wave * kPhotonFields * N * 64 : 0);
+    R *tab = tab_all + (N > MB ? wave * PPL * kTab : 0);
     const double *wf = partials && nchunks == 1 ? wfac : nullptr;
     const uint16_t *hl = H == 0 ? hel : nullptr;
     auto tile_of = [nchunks](int64_t it) -> int64_t { return nchunks == 1 ? it : it / nchunks; };
-    if constexpr (PF == 0) {
+    if constexpr (PF == 0 && PPL == 1) {
         for (; item < end; item += stride) {
             const int64_t tile = tile_of(item);
             const int chunk = static_cast<int>(item - tile * nchunks);
             const PointLoad<N> q = load_point<N>(mom, ld, point_column(index, npts, tile, lane), wf, hl);
             me2_compute<R, N, MB, H, CL>(q, npts, tile, chunk, nchunks, coef, out, ld_out, partials,
                                          wout, flags, tab, lane);
+        }
+    } else if constexpr (PF == 0) {
+        for (; item < end; item += stride) {
+            const int64_t group = tile_of(item);
+            const int chunk = static_cast<int>(item - group * nchunks);
+            PointLoad<N> q[PPL];
+#pragma unroll
+            for (int p = 0; p < PPL; ++p)
+                q[p] = load_point<N>(mom, ld, point_column(index, npts, group * PPL + p, lane), wf, hl);
+            // unconditional, so that the walks can share one basic block: a
+            // tile past the last one (only in the last group) holds no valid
+            // point, stores nothing and writes a zero tile sum into the
+            // spare slot the partial-sum buffer keeps after the last tile
+#pragma unroll
+            for (int p = 0; p < PPL; ++p)
+                me2_compute<R, N, MB, H, CL>(q[p], npts, group * PPL + p, chunk, nchunks, coef, out,
+                                             ld_out, partials, wout, flags, tab + p * kTab, lane);
         }
     } else {
         // Loads for items past the last one read the last tile again (their
@@ -236,11 +260,11 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
     }
 }
 
-template <typename R, int N, int MB, int H, int CL, int WPB, int PF = 0, int WPE = 0>
+template <typename R, int N, int MB, int H, int CL, int WPB, int PF = 0, int WPE = 0, int PPL = 1>
 constexpr Me2Variant variant()
 {
-    return Me2Variant{std::is_same<R, float>::value ? 1 : 0, N, MB, H, CL, WPB, PF, WPE,
-                      reinterpret_cast<const void *>(&me2_kernel<R, N, MB, H, CL, WPB, PF, WPE>)};
+    return Me2Variant{std::is_same<R, float>::value ? 1 : 0, N, MB, H, CL, WPB, PF, WPE, PPL,
+                      reinterpret_cast<const void *>(&me2_kernel<R, N, MB, H, CL, WPB, PF, WPE, PPL>)};
 }
 
 }  // namespace heget

@@ -74,7 +74,7 @@ static int64_t resident_blocks(const Me2Variant &v)
 hipError_t launch_me2(const Me2Variant &v, const Me2Args &a, hipStream_t stream)
 {
     const int64_t ntiles = (a.count + 63) / 64;
-    const int64_t items = ntiles * a.nchunks;
+    const int64_t items = (ntiles + v.ppl - 1) / v.ppl * a.nchunks;
     if (items == 0) return hipSuccess;
     int64_t blocks = (items + v.wpb - 1) / v.wpb;
     if (v.pf) {

@@ -7,8 +7,8 @@
 namespace heget {
 
 extern const Me2Variant kShapesF32Lo[] = {
-    variant<float, 2, 2, 2, 1, 4>(), variant<float, 2, 2, 2, 2, 4>(), variant<float, 2, 2, 4, 2, 4>(), variant<float, 2, 2, 1, 2, 4>(), variant<float, 2, 2, 4, 2, 1>(), variant<float, 2, 2, 4, 2, 1, 1>(),
-    variant<float, 3, 3, 8, 2, 1>(), variant<float, 3, 3, 4, 2, 1>(), variant<float, 3, 3, 4, 2, 4>(), variant<float, 3, 3, 2, 2, 4>(), variant<float, 3, 3, 2, 1, 4>(), variant<float, 3, 3, 1, 2, 4>(), variant<float, 3, 3, 8, 2, 4>(), variant<float, 3, 3, 4, 2, 1, 1>(),
+    variant<float, 2, 2, 2, 1, 4>(), variant<float, 2, 2, 2, 2, 4>(), variant<float, 2, 2, 4, 2, 4>(), variant<float, 2, 2, 1, 2, 4>(), variant<float, 2, 2, 4, 2, 1>(), variant<float, 2, 2, 4, 2, 1, 1>(), variant<float, 2, 2, 4, 2, 4, 0, 0, 2>(),
+    variant<float, 3, 3, 8, 2, 1>(), variant<float, 3, 3, 8, 2, 1, 0, 0, 2>(), variant<float, 3, 3, 4, 2, 1, 0, 0, 2>(), variant<float, 3, 3, 4, 2, 1>(), variant<float, 3, 3, 4, 2, 4>(), variant<float, 3, 3, 2, 2, 4>(), variant<float, 3, 3, 2, 1, 4>(), variant<float, 3, 3, 1, 2, 4>(), variant<float, 3, 3, 8, 2, 4>(), variant<float, 3, 3, 4, 2, 1, 1>(),
     variant<float, 4, 4, 16, 3, 1, 0>(), variant<float, 4, 4, 16, 3, 1, 1>(), variant<float, 4, 4, 16, 3, 1, 0, 2>(), variant<float, 4, 4, 16, 4, 1, 0>(), variant<float, 4, 4, 16, 2, 1, 1>(), variant<float, 4, 4, 16, 2, 1>(), variant<float, 4, 4, 2, 2, 1>(), variant<float, 4, 4, 2, 2, 4>(), variant<float, 4, 4, 2, 1, 4>(), variant<float, 4, 3, 2, 2, 4>(), variant<float, 4, 3, 4, 2, 4>(), variant<float, 4, 4, 1, 2, 4>(), variant<float, 4, 4, 1, 2, 1>(), variant<float, 4, 4, 16, 2, 4>(), variant<float, 4, 4, 4, 2, 1>(), variant<float, 4, 4, 16, 2, 4, 1>(), variant<float, 4, 4, 16, 3, 1>(), variant<float, 4, 4, 4, 3, 1, 1>(),
 };
 extern const int kShapesF32LoCount = sizeof(kShapesF32Lo) / sizeof(Me2Variant);

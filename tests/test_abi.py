@@ -163,7 +163,7 @@ def test_flop_count_of_every_shape():
                     H.set_kernel_shape(n, prec, shape)
                     f, got = H.me2_flops(n, prec)
                     assert got == shape
-                    mb, h, cl, wpb, pf, wpe = shape
+                    mb, h, cl, wpb, pf, wpe, ppl = shape
                     ref = _flops_unshared(n, mb, h, cl)
                     if h == 1 or n > mb:
                         assert f == ref, (n, shape, f, ref)

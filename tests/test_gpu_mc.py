@@ -127,6 +127,30 @@ def test_xsec_matches_oracle_same_sample(H, orc, n, mode, extra, npoints):
         assert abs(got["sigma_fb"] / want["sigma_fb"] - 1) < tol
 
 
+@pytest.mark.parametrize("n", [2, 3])
+def test_xsec_two_points_per_lane_shapes(H, orc, n):
+    """The weighted pass of every two-points-per-lane shape (an odd number of
+    64-point tiles, so the last work item holds one real tile and one past the
+    end) against the oracle on the same sample."""
+    kw = dict(seed=5, npoints=1300, pt_min=20.0, eta_max=2.5, dr_min=0.4, sqrt_s=700.0)  # 21, 19 tiles
+    try:
+        for prec, tol in (("FP64", 1e-10), ("FP32", 1e-5)):
+            P = getattr(H, prec)
+            shapes = [s for s in H.kernel_shapes(n, P) if s[6] == 2]
+            assert shapes, (n, prec)
+            hc, oc = _cfgs(H, orc, H.FIXED_SHAT, prec=P, **kw)
+            want = orc.xsec(n, oc)
+            for shape in shapes:
+                H.set_kernel_shape(n, P, shape)
+                got = H.xsec(n, hc)
+                print(n, prec, shape, got["sigma_fb"], want["sigma_fb"], got["n_acc"], flush=True)
+                assert got["n_acc"] == want["n_acc"] and (got["n_acc"] + 63) // 64 % 2 == 1
+                assert abs(got["sigma_fb"] / want["sigma_fb"] - 1) < tol
+    finally:
+        H.set_kernel_shape(n, H.FP64)
+        H.set_kernel_shape(n, H.FP32)
+
+
 @pytest.mark.parametrize("npoints", [1, 255, 256, 257, 1023, 4097])
 def test_compaction_edges_match_oracle(H, orc, npoints):
     """Survivor counts and sigma across block edges (256-point blocks, the
