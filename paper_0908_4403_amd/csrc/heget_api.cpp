@@ -629,7 +629,7 @@ heget_status enqueue_generation(int n, const heget_config &c, const McBufs &b, h
     gp.clear_word = clear;
     gp.hel_out = b.hel;
     HG_HIP(heget::launch_gen(n, gp, b.mom, np, b.wfac, b.flag, b.bcount, s));
-    HG_HIP(heget::launch_compact(b.flag, np, b.bcount, b.index, b.d_count, s));
+    HG_HIP(heget::launch_compact(b.bcount, b.flag, np, b.index, b.d_count, s));
     return HEGET_OK;
 }
 

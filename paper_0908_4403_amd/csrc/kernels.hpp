@@ -91,7 +91,9 @@ hipError_t launch_gen(int n, const GenParams &g, double *mom, int64_t ld, double
                       uint8_t *flag, int32_t *block_count, hipStream_t stream);
 // Survivor list: index[offset_b + rank] = point, in point order, with the
 // offsets summed from the per-block counts; the survivor total -> *d_count.
-hipError_t launch_compact(const uint8_t *flag, int64_t np, const int32_t *counts, int32_t *index,
+// For more than 2^20 points the counts are first scanned into offsets in
+// place (so `counts` is overwritten).
+hipError_t launch_compact(int32_t *counts, const uint8_t *flag, int64_t np, int32_t *index,
                           int64_t *d_count, hipStream_t stream);
 
 // Event records of a cross-section call, per generated point of g: w_all = 0,

@@ -4,7 +4,7 @@
 // reduction gives sigma and its error.  All FP64.
 //
 // Determinism: compaction keeps point order (block counts -> each block's
-// offset summed from its predecessors' counts -> in-block ballot ranks), and
+// offset, the sum of its predecessors' counts -> in-block ballot ranks), and
 // every sum is a fixed tree (64-point tiles by a fixed tree of cross-lane
 // moves, tiles in index order), so a configuration gives bitwise the same
 // sigma on every run.
@@ -103,29 +103,83 @@ gen_kernel(GenParams g, double *__restrict__ mom, int64_t ld, double *__restrict
     }
 }
 
+// Exclusive prefix sums of the nb per-block counts, in place, and their total
+// into *d_count: one workgroup of 1024 threads walks the counts in chunks of
+// 4096 (four consecutive counts per thread), carrying the running total.
+// Used for large point counts, where the blocks of compact_kernel would
+// otherwise each sum all their predecessors' counts (work growing as nb^2).
+constexpr int kScanThreads = 1024;
+
+__global__ void __launch_bounds__(kScanThreads)
+block_scan_kernel(int32_t *__restrict__ counts, int nb, int64_t *__restrict__ d_count)
+{
+    __shared__ int wave_tot[kScanThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int64_t carry = 0;
+    for (int base = 0; base < nb; base += 4 * kScanThreads) {
+        int v[4], own = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int idx = base + 4 * t + j;
+            v[j] = idx < nb ? counts[idx] : 0;
+            own += v[j];
+        }
+        // inclusive scan of `own` over the wave, then over the waves
+        int inc = own;
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) {
+            const int up = __shfl_up(inc, m, 64);
+            if (lane >= m) inc += up;
+        }
+        if (lane == 63) wave_tot[w] = inc;
+        __syncthreads();
+        int before = 0, chunk = 0;
+        for (int k = 0; k < kScanThreads / 64; ++k) {
+            if (k < w) before += wave_tot[k];
+            chunk += wave_tot[k];
+        }
+        int run = static_cast<int>(carry) + before + inc - own;  // offsets stay below 2^31
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int idx = base + 4 * t + j;
+            if (idx < nb) counts[idx] = run;
+            run += v[j];
+        }
+        carry += chunk;
+        __syncthreads();  // wave_tot is rewritten by the next chunk
+    }
+    if (t == 0) *d_count = carry;
+}
+
 // Survivor list: index[offset_b + rank] = point, in point order, where block b
-// (256 points) finds offset_b, the survivors of blocks 0..b-1, by summing
-// their counts itself (at most a few KiB of L2-resident reads per block, so
-// no separate scan pass); the last block writes the total to *d_count.
+// (256 points) takes offset_b, the survivors of blocks 0..b-1, from `counts`
+// already scanned into offsets (scanned = 1, block_scan_kernel wrote
+// *d_count), or sums its predecessors' counts itself (a few KiB of
+// L2-resident reads per block at the sizes this is used for, so no separate
+// scan pass; the last block writes the total to *d_count).
 __global__ void __launch_bounds__(256)
 compact_kernel(const uint8_t *__restrict__ flag, int64_t np, const int32_t *__restrict__ counts,
-               int nb, int32_t *__restrict__ index, int64_t *__restrict__ d_count)
+               int nb, int scanned, int32_t *__restrict__ index, int64_t *__restrict__ d_count)
 {
     __shared__ int part[4];
     __shared__ int wave_count[4];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    // offset: the counts of blocks 0..b-1, four per 16-byte load (the count
-    // buffer is 256-byte aligned), loads batched so their latencies overlap
     const int b = static_cast<int>(blockIdx.x);
-    const int4 *c4 = reinterpret_cast<const int4 *>(counts);
-    const int nfull = b >> 2;
     int s = 0;
+    if (scanned) {
+        s = t == 0 ? counts[b] : 0;
+    } else {
+        // the counts of blocks 0..b-1, four per 16-byte load (the count
+        // buffer is 256-byte aligned), loads batched so their latencies overlap
+        const int4 *c4 = reinterpret_cast<const int4 *>(counts);
+        const int nfull = b >> 2;
 #pragma unroll 4
-    for (int j = t; j < nfull; j += 256) {
-        const int4 v = c4[j];
-        s += (v.x + v.y) + (v.z + v.w);
+        for (int j = t; j < nfull; j += 256) {
+            const int4 v = c4[j];
+            s += (v.x + v.y) + (v.z + v.w);
+        }
+        if (t < b - (nfull << 2)) s += counts[(nfull << 2) + t];
     }
-    if (t < b - (nfull << 2)) s += counts[(nfull << 2) + t];
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + t;
@@ -141,7 +195,7 @@ compact_kernel(const uint8_t *__restrict__ flag, int64_t np, const int32_t *__re
     int base = offset;
     for (int k = 0; k < w; ++k) base += wave_count[k];
     if (f) index[base + rank] = static_cast<int32_t>(i);
-    if (t == 0 && b == nb - 1)
+    if (!scanned && t == 0 && b == nb - 1)
         *d_count = offset + wave_count[0] + wave_count[1] + wave_count[2] + wave_count[3];
 }
 
@@ -434,13 +488,21 @@ hipError_t launch_event_scatter(const int32_t *index, const double *w, const int
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const uint8_t *flag, int64_t np, const int32_t *counts, int32_t *index,
+// Above this many 256-point blocks (2^20 points) the block counts are scanned
+// by one workgroup first instead of each block summing its predecessors'.
+constexpr int64_t kScanAboveBlocks = 4096;
+
+hipError_t launch_compact(int32_t *counts, const uint8_t *flag, int64_t np, int32_t *index,
                           int64_t *d_count, hipStream_t stream)
 {
     const int64_t blocks = (np + 255) / 256;
     if (blocks == 0) return hipSuccess;
+    const int scanned = blocks > kScanAboveBlocks ? 1 : 0;
+    if (scanned)
+        hipLaunchKernelGGL(block_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, counts,
+                           static_cast<int>(blocks), d_count);
     hipLaunchKernelGGL(compact_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
-                       flag, np, counts, static_cast<int>(blocks), index, d_count);
+                       flag, np, counts, static_cast<int>(blocks), scanned, index, d_count);
     return hipGetLastError();
 }
 

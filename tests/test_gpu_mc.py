@@ -168,6 +168,25 @@ def test_compaction_edges_match_oracle(H, orc, npoints):
             assert abs(got["sigma_fb"] / want["sigma_fb"] - 1) < 1e-10
 
 
+@pytest.mark.parametrize("npoints", [(1 << 20) + 12345, 3 * 4096 * 256 + 1000])
+def test_compaction_with_scanned_offsets_matches_oracle(H, orc, npoints):
+    """Above 2^20 points the block counts are scanned by one workgroup in
+    chunks of 4096 (here one partial chunk, and three full chunks plus a
+    partial one): survivor count exact and sigma at the FP64 bar, with cuts
+    that keep most, some and none of the points."""
+    for pt_min in (20.0, 200.0, 300.0):
+        kw = dict(seed=23, npoints=npoints, sqrt_s=500.0, pt_min=pt_min, eta_max=2.5, dr_min=0.0)
+        hc, oc = _cfgs(H, orc, H.FIXED_SHAT, prec=H.FP64, **kw)
+        got = H.xsec(2, hc)
+        want = orc.xsec(2, oc)
+        print(npoints, pt_min, got["n_acc"], want["n_acc"], flush=True)
+        assert got["n_gen"] == npoints and got["n_acc"] == want["n_acc"], (pt_min, got, want)
+        if want["n_acc"] == 0:
+            assert got["sigma_fb"] == 0.0
+        else:
+            assert abs(got["sigma_fb"] / want["sigma_fb"] - 1) < 1e-10
+
+
 def test_xsec_deterministic_and_empty(H):
     cfg = H.Config(prec=H.FP32, seed=5, npoints=50000 + 3, sqrt_s=1000.0)
     a = H.xsec(4, cfg)
