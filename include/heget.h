@@ -280,10 +280,16 @@ heget_status heget_timing_read(double *me2_ms, int64_t *me2_launches, int reset)
  *   points_per_lane      points each lane evaluates per work item (1, or 2
  *                        with prefetch 0): a work item is that many 64-point
  *                        tiles whose walks run as independent instruction
- *                        streams */
+ *                        streams
+ *   prefix_sets          0: the levels above the unrolled subtree walk every
+ *                        ordered prefix; 1: they walk prefix sets, summing the
+ *                        currents of all orderings of a set (subset recursion)
+ *                        before the subtree, which then runs once per set --
+ *                        the current reuse of the MadGraph program carried to
+ *                        the meeting point of the two ends (Appendix A.1) */
 typedef struct {
     int32_t unrolled, helicities_per_walk, closing, waves_per_block, prefetch, waves_per_simd,
-        points_per_lane;
+        points_per_lane, prefix_sets;
 } heget_shape;
 
 /* Algorithmic floating-point operations per point of the amplitude kernel

@@ -66,11 +66,12 @@ class _Config(C.Structure):
 class Shape(C.Structure):
     _fields_ = [("unrolled", C.c_int32), ("helicities_per_walk", C.c_int32),
                 ("closing", C.c_int32), ("waves_per_block", C.c_int32), ("prefetch", C.c_int32),
-                ("waves_per_simd", C.c_int32), ("points_per_lane", C.c_int32)]
+                ("waves_per_simd", C.c_int32), ("points_per_lane", C.c_int32),
+                ("prefix_sets", C.c_int32)]
 
     def as_tuple(self):
         return (self.unrolled, self.helicities_per_walk, self.closing, self.waves_per_block,
-                self.prefetch, self.waves_per_simd, self.points_per_lane)
+                self.prefetch, self.waves_per_simd, self.points_per_lane, self.prefix_sets)
 
 
 class Result(C.Structure):
@@ -375,7 +376,7 @@ def timing_read(reset: bool = True):
 
 
 SHAPE_FIELDS = ("unrolled", "helicities_per_walk", "closing", "waves_per_block", "prefetch",
-                "waves_per_simd", "points_per_lane")
+                "waves_per_simd", "points_per_lane", "prefix_sets")
 
 
 def me2_flops(n: int, prec: int = FP32):

@@ -277,15 +277,15 @@ double me2_coef(int n, double alpha, double charge)
     return 2.0 * std::pow(e2q2, n);
 }
 
-double me2_flops_per_point(int n, int mb, int h, int cl);
+double me2_flops_per_point(int n, int mb, int h, int cl, int ps = 0);
 
 // Helicity chunks per work item: enough wave-sized items for small batches
 // (>= 8192), and no item above ~2e8 flops so the tail of a launch stays short.
-int plan_chunks_shape(int n, int mb, int h, int cl, int64_t points_expected)
+int plan_chunks_shape(int n, int mb, int h, int cl, int ps, int64_t points_expected)
 {
     const int passes = (1 << n) / h;
     const int64_t tiles = (points_expected + 63) / 64;
-    const double item_flops = 64.0 * me2_flops_per_point(n, mb, h, cl);
+    const double item_flops = 64.0 * me2_flops_per_point(n, mb, h, cl, ps);
     int c = 1;
     while (c < passes && (tiles * c < 8192 || item_flops / c > 2e8)) c *= 2;
     return c;
@@ -293,7 +293,7 @@ int plan_chunks_shape(int n, int mb, int h, int cl, int64_t points_expected)
 
 int plan_chunks(const heget::Me2Variant &v, int64_t points_expected)
 {
-    return plan_chunks_shape(v.n, v.mb, v.h, v.cl, points_expected);
+    return plan_chunks_shape(v.n, v.mb, v.h, v.cl, v.ps, points_expected);
 }
 
 // Shape chosen by the autotuner (or loaded from the tuning cache) per (prec, n).
@@ -306,25 +306,25 @@ const heget::Me2Variant *pick_variant(int prec, int n)
 }
 
 const heget::Me2Variant *find_variant(int prec, int n, int mb, int h, int cl, int wpb, int pf, int wpe,
-                                      int ppl)
+                                      int ppl, int ps)
 {
     int cnt = 0;
     const heget::Me2Variant *v = heget::me2_variants(&cnt);
     for (int i = 0; i < cnt; ++i)
         if (v[i].prec == prec && v[i].n == n && v[i].mb == mb && v[i].h == h && v[i].cl == cl &&
-            v[i].wpb == wpb && v[i].pf == pf && v[i].wpe == wpe && v[i].ppl == ppl)
+            v[i].wpb == wpb && v[i].pf == pf && v[i].wpe == wpe && v[i].ppl == ppl && v[i].ps == ps)
             return &v[i];
     return nullptr;
 }
 
 heget_shape shape_of(const heget::Me2Variant &v)
 {
-    return heget_shape{v.mb, v.h, v.cl, v.wpb, v.pf, v.wpe, v.ppl};
+    return heget_shape{v.mb, v.h, v.cl, v.wpb, v.pf, v.wpe, v.ppl, v.ps};
 }
 
 // Tuning cache: one JSON object per line,
 // {"arch": "gfx950", "prec": 1, "n": 4, "mb": 4, "h": 2, "cl": 2, "wpb": 4, "pf": 0, "wpe": 2,
-//  "ppl": 1, "ms": 0.48, "points": 1048576}
+//  "ppl": 1, "ps": 0, "ms": 0.48, "points": 1048576}
 void load_tuning_cache()
 {
     const char *path = std::getenv("HEGET_TUNING_CACHE");
@@ -334,11 +334,11 @@ void load_tuning_cache()
     char line[512];
     while (std::fgets(line, sizeof line, f)) {
         char arch[64] = {0};
-        int prec, n, mb, h, cl, wpb, pf, wpe, ppl;
-        if (std::sscanf(line, " {\"arch\": \"%63[^\"]\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d, \"wpe\": %d, \"ppl\": %d",
-                        arch, &prec, &n, &mb, &h, &cl, &wpb, &pf, &wpe, &ppl) == 10 &&
+        int prec, n, mb, h, cl, wpb, pf, wpe, ppl, ps;
+        if (std::sscanf(line, " {\"arch\": \"%63[^\"]\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d, \"wpe\": %d, \"ppl\": %d, \"ps\": %d",
+                        arch, &prec, &n, &mb, &h, &cl, &wpb, &pf, &wpe, &ppl, &ps) == 11 &&
             g_arch == arch && prec >= 0 && prec < 2 && n >= 2 && n <= 8) {
-            const heget::Me2Variant *v = find_variant(prec, n, mb, h, cl, wpb, pf, wpe, ppl);
+            const heget::Me2Variant *v = find_variant(prec, n, mb, h, cl, wpb, pf, wpe, ppl, ps);
             if (v) g_tuned[prec][n] = v;
         }
     }
@@ -361,8 +361,8 @@ void save_tuning_cache(const heget::Me2Variant &v, double ms, int64_t points)
     }
     if (FILE *f = std::fopen(path, "w")) {
         for (const std::string &l : keep) std::fputs(l.c_str(), f);
-        std::fprintf(f, "{\"arch\": \"%s\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d, \"wpe\": %d, \"ppl\": %d, \"ms\": %.6f, \"points\": %lld}\n",
-                     g_arch.c_str(), v.prec, v.n, v.mb, v.h, v.cl, v.wpb, v.pf, v.wpe, v.ppl, ms,
+        std::fprintf(f, "{\"arch\": \"%s\", \"prec\": %d, \"n\": %d, \"mb\": %d, \"h\": %d, \"cl\": %d, \"wpb\": %d, \"pf\": %d, \"wpe\": %d, \"ppl\": %d, \"ps\": %d, \"ms\": %.6f, \"points\": %lld}\n",
+                     g_arch.c_str(), v.prec, v.n, v.mb, v.h, v.cl, v.wpb, v.pf, v.wpe, v.ppl, v.ps, ms,
                      static_cast<long long>(points));
         std::fclose(f);
     }
@@ -466,7 +466,7 @@ struct Walk {
 
 }  // namespace flops
 
-double me2_flops_per_point(int n, int mb, int h, int cl)
+double me2_flops_per_point(int n, int mb, int h, int cl, int ps)
 {
     flops::Walk w;
     w.n = n;
@@ -475,7 +475,22 @@ double me2_flops_per_point(int n, int mb, int h, int cl)
     while ((1 << w.b) < h) ++w.b;
     w.cl = cl;
     w.shared = n <= mb;
-    w.below(0u, n <= mb ? n : mb);
+    const int k = n - mb;
+    if (ps == 1 && k >= 2) {
+        // prefix sets: per k-subset of the photons, its vertex blocks and the
+        // subset recursion over its subsets Q (momentum part 14, a vertex half
+        // 16, |Q| - 1 vertex halves added 20 each and a propagator half 20,
+        // per helicity), then the subtree over the other photons
+        for (unsigned set = 0; set < (1u << n); ++set) {
+            if (__builtin_popcount(set) != k) continue;
+            w.total += 4.0 * k;
+            for (unsigned q = 1; q < (1u << k); ++q)
+                w.total += 14.0 + (16.0 + 20.0 * (__builtin_popcount(q) - 1) + 20.0) * h;
+            w.below(set, mb);
+        }
+    } else {
+        w.below(0u, n <= mb ? n : mb);
+    }
     w.total += 4.0 * h;
     return w.total * double(1 << n) / double(h);
 }
@@ -776,7 +791,7 @@ struct Arena {
 
 struct SliceBufs {
     McBufs b;
-    int mb, h, cl;
+    int mb, h, cl, ps;
 };
 
 void carve_batch(Arena &ar, int ncfg, const int *n, const heget_config *cfgs, int schedule,
@@ -789,15 +804,16 @@ void carve_batch(Arena &ar, int ncfg, const int *n, const heget_config *cfgs, in
         const int64_t np = cfgs[s].npoints;
         SliceBufs &sl = sb[s];
         if (schedule == 1) {
-            heget::me2_batch_shape(cfgs[s].prec, n[s], &sl.mb, &sl.h, &sl.cl);
+            heget::me2_batch_shape(cfgs[s].prec, n[s], &sl.mb, &sl.h, &sl.cl, &sl.ps);
         } else {
             const heget::Me2Variant *v = pick_variant(cfgs[s].prec, n[s]);
             sl.mb = v->mb;
             sl.h = v->h;
             sl.cl = v->cl;
+            sl.ps = v->ps;
         }
         McBufs &b = sl.b;
-        b.nchunks = plan_chunks_shape(n[s], sl.mb, sl.h, sl.cl, np / 2);
+        b.nchunks = plan_chunks_shape(n[s], sl.mb, sl.h, sl.cl, sl.ps, np / 2);
         b.mom = ar.take<double>(size_t(n[s] + 2) * 4 * size_t(np));
         b.wfac = ar.take<double>(size_t(np));
         b.flag = ar.take<uint8_t>(size_t(np));
@@ -849,7 +865,7 @@ heget_status batch_enqueue(int ncfg, const int *n, const heget_config *cfgs, Sli
     std::vector<int> order(ncfg);
     for (int i = 0; i < ncfg; ++i) order[i] = i;
     auto cost = [&](int x) {
-        return me2_flops_per_point(n[x], sb[x].mb, sb[x].h, sb[x].cl) / sb[x].b.nchunks;
+        return me2_flops_per_point(n[x], sb[x].mb, sb[x].h, sb[x].cl, sb[x].ps) / sb[x].b.nchunks;
     };
     std::sort(order.begin(), order.end(), [&](int x, int y) {
         const double cx = cost(x), cy = cost(y);
@@ -1581,7 +1597,7 @@ heget_status heget_set_kernel_shape(int n, heget_prec prec, const heget_shape *s
     const heget::Me2Variant *v =
         find_variant(prec, n, shape->unrolled, shape->helicities_per_walk, shape->closing,
                      shape->waves_per_block, shape->prefetch, shape->waves_per_simd,
-                     shape->points_per_lane);
+                     shape->points_per_lane, shape->prefix_sets);
     if (!v) return fail(HEGET_ERR_ARG, "no compiled kernel shape with these parameters");
     g_tuned[prec][n] = v;
     return HEGET_OK;
@@ -1651,7 +1667,7 @@ heget_status heget_me2_flops(int n, heget_prec prec, double *flops_per_point, he
     if (!flops_per_point) return fail(HEGET_ERR_ARG, "null pointer");
     const heget::Me2Variant *v = pick_variant(prec, n);
     if (!v) return fail(HEGET_ERR_ARG, "no compiled amplitude kernel for this n/precision");
-    *flops_per_point = me2_flops_per_point(n, v->mb, v->h, v->cl);
+    *flops_per_point = me2_flops_per_point(n, v->mb, v->h, v->cl, v->ps);
     if (shape) *shape = shape_of(*v);
     return HEGET_OK;
 }

@@ -21,6 +21,7 @@ struct Me2Variant {
     int pf;     // 1: resident waves loop over the items, loading the next one ahead
     int wpe;    // minimum waves per SIMD the kernel is compiled for (0: no bound)
     int ppl;    // points per lane: 64-point tiles per work item (1 unless pf = 0)
+    int ps;     // 1: top levels walked by prefix sets (currents summed over their orderings)
     const void *func;  // kernel symbol
 };
 
@@ -80,8 +81,8 @@ hipError_t launch_batch_plan(const BatchDesc &b, hipStream_t stream);
 // prec 0 = FP64, 1 = FP32; grid = number of persistent blocks of 256 threads.
 hipError_t launch_me2_batch(int prec, const BatchDesc &b, int grid, hipStream_t stream);
 int me2_batch_blocks_per_cu(int prec);
-// (unrolled depth, helicities per walk, closing depth) of the mixed kernel for n
-void me2_batch_shape(int prec, int n, int *mb, int *h, int *cl);
+// (unrolled depth, helicities per walk, closing depth, prefix sets) of the mixed kernel for n
+void me2_batch_shape(int prec, int n, int *mb, int *h, int *cl, int *ps);
 
 // Phase-space generation (FP64): momenta of every point in SoA and its
 // weight (kind 0: Phi_n or 0 if cut; kind 1: full eq. (1)-(2) factor without

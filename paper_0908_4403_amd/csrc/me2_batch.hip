@@ -16,6 +16,7 @@ struct BatchShape {
     static constexpr int mb(int n) { return n < 4 ? n : 4; }
     static constexpr int h = fp32 ? 2 : 1;
     static constexpr int cl = 3;
+    static constexpr int ps(int n) { return n >= 6 ? 1 : 0; }  // prefix sets above the subtree
 };
 
 __device__ __forceinline__ int64_t wave_broadcast(int64_t v)
@@ -41,7 +42,7 @@ __device__ __forceinline__ void batch_item(const SliceDesc &d, int64_t npts, int
                                            unsigned *flags, R *tab, int lane)
 {
     // |M|^2 only: the weighted sums follow in a separate pass
-    me2_item<R, N, BatchShape<R>::mb(N), BatchShape<R>::h, BatchShape<R>::cl, false>(
+    me2_item<R, N, BatchShape<R>::mb(N), BatchShape<R>::h, BatchShape<R>::cl, false, BatchShape<R>::ps(N)>(
         d.mom, d.ld, d.index, nullptr, npts, tile, chunk, d.nchunks, d.coef, d.out, d.ld_out, d.wfac,
         d.partials, nullptr, flags, tab, lane);
 }
@@ -106,16 +107,18 @@ int me2_batch_blocks_per_cu(int prec)
     return blocks;
 }
 
-void me2_batch_shape(int prec, int n, int *mb, int *h, int *cl)
+void me2_batch_shape(int prec, int n, int *mb, int *h, int *cl, int *ps)
 {
     if (prec == 1) {
         *mb = BatchShape<float>::mb(n);
         *h = BatchShape<float>::h;
         *cl = BatchShape<float>::cl;
+        *ps = BatchShape<float>::ps(n);
     } else {
         *mb = BatchShape<double>::mb(n);
         *h = BatchShape<double>::h;
         *cl = BatchShape<double>::cl;
+        *ps = BatchShape<double>::ps(n);
     }
 }
 

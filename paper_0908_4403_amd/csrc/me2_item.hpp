@@ -54,7 +54,7 @@ __device__ __forceinline__ PointLoad<N> load_point(const double *__restrict__ mo
 // compensation, sum of squares) of |M|^2 * wf (the Monte-Carlo weights of
 // eq. (1)-(2)), and the weight itself at wout[i] when wout is set; otherwise
 // |M|^2 of the chunk at out[chunk * ld_out + i].
-template <typename R, int N, int MB, int H, int CL, bool kWeighted = true>
+template <typename R, int N, int MB, int H, int CL, bool kWeighted = true, int PS = 0>
 __device__ __forceinline__ void me2_compute(const PointLoad<N> &q, int64_t npts, int64_t tile,
                                             int chunk, int nchunks, double coef,
                                             double *__restrict__ out, int64_t ld_out,
@@ -121,11 +121,11 @@ __device__ __forceinline__ void me2_compute(const PointLoad<N> &q, int64_t npts,
 
     double s;
     if constexpr (H == 0) {
-        s = tree_one<R, N, MB, CL>(in, tab, lane, q.hel);
+        s = tree_one<R, N, MB, CL, PS>(in, tab, lane, q.hel);
     } else {
         constexpr int kPasses = (1 << N) / H;
         const int ppc = kPasses / nchunks;
-        s = tree_sum<R, N, MB, H, CL>(in, tab, lane, chunk * ppc, (chunk + 1) * ppc);
+        s = tree_sum<R, N, MB, H, CL, PS>(in, tab, lane, chunk * ppc, (chunk + 1) * ppc);
     }
     double me2 = ldexp(coef * (norm / norm_den) * s, 2 * m * (2 - N));
     if (!ok) me2 = __builtin_nan("");
@@ -141,7 +141,7 @@ __device__ __forceinline__ void me2_compute(const PointLoad<N> &q, int64_t npts,
 }
 
 // Load and compute one work item (used by the mixed-n batch kernel).
-template <typename R, int N, int MB, int H, int CL, bool kWeighted = true>
+template <typename R, int N, int MB, int H, int CL, bool kWeighted = true, int PS = 0>
 __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t ld,
                                          const int32_t *__restrict__ index,
                                          const uint16_t *__restrict__ hel, int64_t npts,
@@ -154,7 +154,7 @@ __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t
     const uint32_t src = point_column(index, npts, tile, lane);
     const double *wf = kWeighted && partials && nchunks == 1 ? wfac : nullptr;
     const PointLoad<N> q = load_point<N>(mom, ld, src, wf, H == 0 ? hel : nullptr);
-    me2_compute<R, N, MB, H, CL, kWeighted>(q, npts, tile, chunk, nchunks, coef, out, ld_out,
+    me2_compute<R, N, MB, H, CL, kWeighted, PS>(q, npts, tile, chunk, nchunks, coef, out, ld_out,
                                             partials, wout, flags, tab, lane);
 }
 
@@ -172,7 +172,8 @@ __device__ __forceinline__ void me2_item(const double *__restrict__ mom, int64_t
 // independent instruction streams in one loop body (each with its own LDS
 // photon table), for more instruction-level parallelism per wave; the
 // weighted partial-sum buffer needs one spare tile slot after the last tile.
-template <typename R, int N, int MB, int H, int CL, int WPB, int PF, int WPE, int PPL>
+// PS = 1 walks the top levels by prefix sets (prefix_sets in me2_tree.hpp).
+template <typename R, int N, int MB, int H, int CL, int WPB, int PF, int WPE, int PPL, int PS>
 __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict__ index,
            const uint16_t *__restrict__ hel, const int64_t *__restrict__ d_count, int64_t count,
@@ -214,8 +215,8 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
             const int64_t tile = tile_of(item);
             const int chunk = static_cast<int>(item - tile * nchunks);
             const PointLoad<N> q = load_point<N>(mom, ld, point_column(index, npts, tile, lane), wf, hl);
-            me2_compute<R, N, MB, H, CL>(q, npts, tile, chunk, nchunks, coef, out, ld_out, partials,
-                                         wout, flags, tab, lane);
+            me2_compute<R, N, MB, H, CL, true, PS>(q, npts, tile, chunk, nchunks, coef, out, ld_out,
+                                                   partials, wout, flags, tab, lane);
         }
     } else if constexpr (PF == 0) {
         for (; item < end; item += stride) {
@@ -231,8 +232,9 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
             // spare slot the partial-sum buffer keeps after the last tile
 #pragma unroll
             for (int p = 0; p < PPL; ++p)
-                me2_compute<R, N, MB, H, CL>(q[p], npts, group * PPL + p, chunk, nchunks, coef, out,
-                                             ld_out, partials, wout, flags, tab + p * kTab, lane);
+                me2_compute<R, N, MB, H, CL, true, PS>(q[p], npts, group * PPL + p, chunk, nchunks, coef,
+                                                       out, ld_out, partials, wout, flags, tab + p * kTab,
+                                                       lane);
         }
     } else {
         // Loads for items past the last one read the last tile again (their
@@ -250,8 +252,8 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
             const uint32_t src_after = point_column(index, npts, ahead(item + 2 * stride), lane);
             const int64_t tile = tile_of(item);
             const int chunk = static_cast<int>(item - tile * nchunks);
-            me2_compute<R, N, MB, H, CL>(cur, npts, tile, chunk, nchunks, coef, out, ld_out, partials,
-                                         wout, flags, tab, lane);
+            me2_compute<R, N, MB, H, CL, true, PS>(cur, npts, tile, chunk, nchunks, coef, out, ld_out,
+                                                   partials, wout, flags, tab, lane);
             item += stride;
             if (item >= end) break;
             cur = nxt;
@@ -260,11 +262,12 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
     }
 }
 
-template <typename R, int N, int MB, int H, int CL, int WPB, int PF = 0, int WPE = 0, int PPL = 1>
+template <typename R, int N, int MB, int H, int CL, int WPB, int PF = 0, int WPE = 0, int PPL = 1,
+          int PS = 0>
 constexpr Me2Variant variant()
 {
-    return Me2Variant{std::is_same<R, float>::value ? 1 : 0, N, MB, H, CL, WPB, PF, WPE, PPL,
-                      reinterpret_cast<const void *>(&me2_kernel<R, N, MB, H, CL, WPB, PF, WPE, PPL>)};
+    return Me2Variant{std::is_same<R, float>::value ? 1 : 0, N, MB, H, CL, WPB, PF, WPE, PPL, PS,
+                      reinterpret_cast<const void *>(&me2_kernel<R, N, MB, H, CL, WPB, PF, WPE, PPL, PS>)};
 }
 
 }  // namespace heget

@@ -7,8 +7,8 @@
 namespace heget {
 
 extern const Me2Variant kShapesF32Hi[] = {
-    variant<float, 7, 4, 2, 3, 4>(), variant<float, 7, 4, 1, 3, 4>(), variant<float, 7, 4, 1, 3, 1>(), variant<float, 7, 4, 2, 2, 1, 1>(), variant<float, 7, 4, 2, 2, 4>(), variant<float, 7, 4, 2, 1, 4>(), variant<float, 7, 3, 2, 2, 4>(), variant<float, 7, 4, 1, 2, 4>(), variant<float, 7, 4, 2, 2, 1>(), variant<float, 7, 3, 2, 2, 1>(), variant<float, 7, 4, 2, 3, 1, 1>(),
-    variant<float, 8, 4, 1, 3, 1>(), variant<float, 8, 4, 1, 2, 1>(), variant<float, 8, 4, 1, 2, 4>(), variant<float, 8, 4, 2, 2, 4>(), variant<float, 8, 4, 2, 1, 4>(), variant<float, 8, 3, 2, 2, 4>(), variant<float, 8, 3, 2, 2, 1>(), variant<float, 8, 4, 1, 2, 1, 1>(), variant<float, 8, 4, 2, 3, 4>(), variant<float, 8, 4, 1, 3, 4>(),
+    variant<float, 7, 4, 2, 3, 4, 0, 0, 1, 1>(), variant<float, 7, 4, 2, 3, 4>(), variant<float, 7, 4, 1, 3, 4, 0, 0, 1, 1>(), variant<float, 7, 4, 1, 3, 1, 0, 0, 1, 1>(), variant<float, 7, 4, 1, 3, 4>(), variant<float, 7, 4, 1, 3, 1>(), variant<float, 7, 4, 2, 2, 1, 1>(), variant<float, 7, 4, 2, 2, 4>(), variant<float, 7, 4, 2, 1, 4>(), variant<float, 7, 3, 2, 2, 4>(), variant<float, 7, 4, 1, 2, 4>(), variant<float, 7, 4, 2, 2, 1>(), variant<float, 7, 3, 2, 2, 1>(), variant<float, 7, 4, 2, 3, 1, 1>(),
+    variant<float, 8, 4, 1, 3, 1, 0, 0, 1, 1>(), variant<float, 8, 4, 1, 3, 1>(), variant<float, 8, 4, 1, 3, 4, 0, 0, 1, 1>(), variant<float, 8, 4, 2, 3, 4, 0, 0, 1, 1>(), variant<float, 8, 4, 1, 2, 1>(), variant<float, 8, 4, 1, 2, 4>(), variant<float, 8, 4, 2, 2, 4>(), variant<float, 8, 4, 2, 1, 4>(), variant<float, 8, 3, 2, 2, 4>(), variant<float, 8, 3, 2, 2, 1>(), variant<float, 8, 4, 1, 2, 1, 1>(), variant<float, 8, 4, 2, 3, 4>(), variant<float, 8, 4, 1, 3, 4>(),
 };
 extern const int kShapesF32HiCount = sizeof(kShapesF32Hi) / sizeof(Me2Variant);
 

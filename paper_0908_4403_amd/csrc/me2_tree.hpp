@@ -149,6 +149,15 @@ struct Prop {
     R m, p, x, y;
 };
 
+// d * (q-, q+, qx, qy), d = -1/q^2, for an internal momentum q.
+template <typename R>
+__device__ __forceinline__ Prop<R> prop_at(const LMom<R> &q)
+{
+    const R q2 = q.p * q.m - q.x * q.x - q.y * q.y;
+    const R d = neg_recip(q2);
+    return {d * q.m, d * q.p, d * q.x, d * q.y};
+}
+
 template <typename R>
 __device__ __forceinline__ Prop<R> propagate(const LMom<R> &q, const LMom<R> &k, LMom<R> &qn)
 {
@@ -515,6 +524,85 @@ __device__ __forceinline__ void top_levels(const R *tab, int lane, uint32_t rem,
     }
 }
 
+// Compile-time loop over I = B .. E-1, calling f(integral_constant<int, I>).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(static_cast<F &&>(f));
+    }
+}
+
+// The next bitmask with the same number of set bits (Gosper's rule,
+// HAKMEM item 175): subsets of one size in increasing order.
+__device__ __forceinline__ uint32_t next_subset(uint32_t v)
+{
+    const uint32_t t = v | (v - 1u);
+    return (t + 1u) | (((~t & (t + 1u)) - 1u) >> (__builtin_ctz(v) + 1));
+}
+
+// Prefix sets (shape field prefix_sets = 1) for the top n-MB levels.  Every
+// ordering of the same prefix set P reaches the subtree over the remaining
+// photons with the same momentum -p2 + sum_{i in P} k_i, and the subtree is
+// linear in the current it is entered with.  So the currents of all orderings
+// of P are summed first and the subtree runs once per set, C(n, n-MB) times
+// instead of n!/MB! times.  The sum is the subset recursion over the subsets
+// Q of P (momenta q_Q = -p2 + sum_{i in Q} k_i, J(empty) = the vbar current):
+//     J(Q) = d(q_Q) P(q_Q) sum_{j in Q} V_j J(Q \ j),
+// one propagator per subset for the vertex halves of all its last photons,
+// as the four-photon closing does for its pairs.  The sums over the orderings
+// of P are taken in the working precision; the subtree's closings enter the
+// FP64 ordering sum as before.
+template <typename R, int N, int MB, int H, int CL>
+__device__ __forceinline__ void prefix_sets(const R *tab, int lane, uint32_t cfg0, const LMom<R> &p1,
+                                            const Chain<R, H> &c0, const LMom<R> &q0, Acc<H> &acc)
+{
+    constexpr int K = N - MB;
+    constexpr uint32_t kFull = (1u << K) - 1u;
+#pragma nounroll
+    for (uint32_t set = kFull; set < (1u << N); set = next_subset(set)) {
+        LMom<R> kq[K];
+        Vert<R, H> vq[K];
+        uint32_t m = set;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const int j = __builtin_ctz(m);
+            m &= m - 1u;
+            kq[s] = lds_photon<R, N>(tab, j, lane);
+            vq[s] = make_vert<R, H>(kq[s], cfg0, j);
+        }
+        Chain<R, H> J[1 << K];
+        LMom<R> q[1 << K];
+        J[0] = c0;
+        q[0] = q0;
+        // every proper subset precedes its supersets in increasing order
+        static_for<1, (1 << K)>([&](auto mi) {
+            constexpr uint32_t mask = decltype(mi)::value;
+            constexpr int low = __builtin_ctz(mask);
+            const LMom<R> &qb = q[mask & (mask - 1u)];
+            q[mask] = {qb.p + kq[low].p, qb.m + kq[low].m, qb.x + kq[low].x, qb.y + kq[low].y, R(0), R(0)};
+            Half<R, H> sl = vertex_half<R, H>(vq[low], J[mask & ~(1u << low)]);
+            for_each_bit<(mask & (mask - 1u))>([&](auto bit) {
+                constexpr int b = decltype(bit)::value;
+                vertex_half_add<R, H>(vq[b], J[mask & ~(1u << b)], sl);
+            });
+            propagator_half<R, H>(prop_at<R>(q[mask]), sl, J[mask]);
+        });
+        const uint32_t rest = ((1u << N) - 1u) & ~set;
+        Slots<R, H, MB> S;
+        m = rest;
+#pragma unroll
+        for (int s = 0; s < MB; ++s) {
+            const int js = __builtin_ctz(m);
+            m &= m - 1u;
+            S.k[s] = lds_photon<R, N>(tab, js, lane);
+            S.v[s] = make_vert<R, H>(S.k[s], cfg0, js);
+        }
+        run_subtree<R, H, MB, CL>(S, p1, J[kFull], q[kFull], acc);
+    }
+}
+
 // Per-point inputs after the FP64 set-up.
 template <typename R, int N>
 struct PointIn {
@@ -525,7 +613,7 @@ struct PointIn {
 
 // Sum over helicity passes [pass0, pass1) of |ordering sum|^2 (scaled units,
 // without the external normalisations).  Each pass covers H configurations.
-template <typename R, int N, int MB, int H, int CL>
+template <typename R, int N, int MB, int H, int CL, int PS = 0>
 __device__ __forceinline__ double tree_sum(const PointIn<R, N> &in, R *tab, int lane, int pass0,
                                            int pass1)
 {
@@ -554,6 +642,8 @@ __device__ __forceinline__ double tree_sum(const PointIn<R, N> &in, R *tab, int 
                 S.v[s] = make_vert<R, H>(in.k[s], cfg0, s);
             }
             run_subtree<R, H, N, CL>(S, in.p1, c0, in.q0, acc);
+        } else if constexpr (PS == 1 && N - MB >= 2) {
+            prefix_sets<R, N, MB, H, CL>(tab, lane, cfg0, in.p1, c0, in.q0, acc);
         } else {
             top_levels<R, N, MB, H, CL, 0>(tab, lane, (1u << N) - 1u, cfg0, in.p1, c0, in.q0, acc);
         }
@@ -566,7 +656,7 @@ __device__ __forceinline__ double tree_sum(const PointIn<R, N> &in, R *tab, int 
 // One walk per lane with the lane's own helicity configuration `cfg` (bit j
 // set = photon j has helicity +1): |ordering sum|^2 of that configuration
 // (scaled units, without the external normalisations).
-template <typename R, int N, int MB, int CL>
+template <typename R, int N, int MB, int CL, int PS = 0>
 __device__ __forceinline__ double tree_one(const PointIn<R, N> &in, R *tab, int lane, uint32_t cfg)
 {
     Chain<R, 1> c0;
@@ -585,6 +675,8 @@ __device__ __forceinline__ double tree_one(const PointIn<R, N> &in, R *tab, int 
             S.v[s] = make_vert<R, 1>(in.k[s], cfg, s);
         }
         run_subtree<R, 1, N, CL>(S, in.p1, c0, in.q0, acc);
+    } else if constexpr (PS == 1 && N - MB >= 2) {
+        prefix_sets<R, N, MB, 1, CL>(tab, lane, cfg, in.p1, c0, in.q0, acc);
     } else {
         top_levels<R, N, MB, 1, CL, 0>(tab, lane, (1u << N) - 1u, cfg, in.p1, c0, in.q0, acc);
     }

@@ -165,7 +165,7 @@ def test_autotune_picks_a_compiled_shape(H, orc, tmp_path, monkeypatch):
     assert r["ms"] > 0
     line = cache.read_text().strip()
     assert (f'"n": 5, "mb": {shape[0]}, "h": {shape[1]}, "cl": {shape[2]}, "wpb": {shape[3]}, '
-            f'"pf": {shape[4]}, "wpe": {shape[5]}, "ppl": {shape[6]}') in line
+            f'"pf": {shape[4]}, "wpe": {shape[5]}, "ppl": {shape[6]}, "ps": {shape[7]}') in line
     ev = cut_events(orc, 5, 1000.0, 17, 100)
     ref, _ = orc.me2_batch(ev)
     assert np.median(np.abs(H.me2(ev, H.FP32) / ref - 1)) <= 1e-5
@@ -181,7 +181,7 @@ def test_resident_loop_many_items_and_chunks(H, orc):
     ev = cut_events(orc, n, 1000.0, 31, 20000)
     ref, _ = orc.me2_batch(ev[::10])
     try:
-        for prec, shape in ((H.FP64, (4, 2, 3, 1, 1, 0, 1)), (H.FP32, (5, 2, 3, 1, 1, 0, 1))):
+        for prec, shape in ((H.FP64, (4, 2, 3, 1, 1, 0, 1, 0)), (H.FP32, (5, 2, 3, 1, 1, 0, 1, 0))):
             H.set_kernel_shape(n, prec, shape)
             rel = np.abs(H.me2(ev, prec)[::10] / ref - 1.0)
             print(f"n={n} prec={prec} shape={shape} max rel {rel.max():.2e} median {np.median(rel):.2e}",
