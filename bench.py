@@ -133,12 +133,12 @@ def mixed_batch(H, torch, prec, steps):
             "sigma_fb": {str(n): r["sigma_fb"] for n, r in zip(ns, res)}}
 
 
-def per_n(H, torch, tune):
+def per_n(H, torch, tune, ns=range(2, 9)):
     """Amplitude kernel alone (heget_me2_device) for n = 2..8 on device-generated
     points (sqrt(shat) = 1 TeV, seed 11, no cuts so every point is a valid input),
     FP32 and FP64, with HIP-event timing of the kernel on its launch stream."""
     out = []
-    for n in range(2, 9):
+    for n in ns:
         npts = 1 << {2: 22, 3: 21, 4: 20, 5: 18, 6: 16, 7: 15, 8: 14}[n]
         mom = torch.empty(((n + 2) * 4, npts), dtype=torch.float64, device="cuda")
         w = torch.empty(npts, dtype=torch.float64, device="cuda")
@@ -373,6 +373,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed n=2..7 batch")
     ap.add_argument("--no-n8", action="store_true", help="skip the n=8 workload (2^18 points at 2 TeV)")
     ap.add_argument("--no-per-n", action="store_true", help="skip the per-n amplitude kernel timings")
+    ap.add_argument("--per-n-list", default="2,3,4,5,6,7,8",
+                    help="photon counts of the per-n section (comma-separated)")
     ap.add_argument("--no-tune", action="store_true", help="use the untuned kernel shapes")
     ap.add_argument("--settle-ms", type=float, default=1000.0,
                     help="untimed passes for this long before the warmup steps (clock ramp-up)")
@@ -433,7 +435,8 @@ def main():
         print(f"bench: mixed batch {mixed['batch_ms']:.2f} ms vs per-n {mixed['one_launch_per_n_ms']:.2f} ms",
               file=sys.stderr, flush=True)
 
-    pern = None if args.no_per_n else per_n(H, torch, not args.no_tune)
+    pern = None if args.no_per_n else per_n(H, torch, not args.no_tune,
+                                            [int(x) for x in args.per_n_list.split(",")])
     n8 = None if args.no_n8 else config_n8(H, torch, workloads["uubar_8a_2TeV_2p18"], 1)
 
     cpu, accuracy = None, None
