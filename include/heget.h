@@ -266,7 +266,11 @@ heget_status heget_timing_read(double *me2_ms, int64_t *me2_launches, int reset)
  *                        close with 6 pair products instead of 12 (in FP32
  *                        kernels with 8 or more helicities per walk each of
  *                        the 6 products is taken in FP64); 4: as 3 with the
- *                        products always in the working precision
+ *                        products always in the working precision; 5: as 4,
+ *                        with the products of complementary splits ({x, y} |
+ *                        {a, b} and {a, b} | {x, y}) summed in the working
+ *                        precision, so that each four-photon closing enters
+ *                        the FP64 ordering sum three times instead of six
  *   waves_per_block      64-lane waves per workgroup
  *   prefetch             0: one wave per 64-point work item; 1: only as many
  *                        waves as the device holds at once, each looping over

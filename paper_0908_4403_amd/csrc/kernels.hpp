@@ -16,7 +16,8 @@ struct Me2Variant {
     int h;      // helicity configurations per tree walk
     int cl;     // closing: 1 = photon by photon, 2 = last pair by pair vectors, 3 = last
                 // four by pair sums at both ends (FP64 products for h >= 8), 4 = as 3
-                // with the products in the working precision
+                // with the products in the working precision, 5 = as 4 with the
+                // products of complementary splits summed before the FP64 sum
     int wpb;    // waves per block
     int pf;     // 1: resident waves loop over the items, loading the next one ahead
     int wpe;    // minimum waves per SIMD the kernel is compiled for (0: no bound)

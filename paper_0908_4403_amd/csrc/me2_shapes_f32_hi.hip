@@ -1,14 +1,15 @@
 // Compiled amplitude-kernel shapes, float, n = 7, 8:
 // variant<R, n, unrolled depth, helicities per walk, closing depth, waves per block,
-// prefetch (resident waves looping over items; default 0)>.
+// prefetch, waves per SIMD, points per lane, prefix sets> (the last four default to
+// 0, 0, 1, 0; the fields of heget_shape).
 // The first entry for each n is the default before tuning.
 #include "me2_item.hpp"
 
 namespace heget {
 
 extern const Me2Variant kShapesF32Hi[] = {
-    variant<float, 7, 4, 2, 3, 4, 0, 0, 1, 1>(), variant<float, 7, 4, 2, 3, 4>(), variant<float, 7, 4, 1, 3, 4, 0, 0, 1, 1>(), variant<float, 7, 4, 1, 3, 1, 0, 0, 1, 1>(), variant<float, 7, 4, 1, 3, 4>(), variant<float, 7, 4, 1, 3, 1>(), variant<float, 7, 4, 2, 2, 1, 1>(), variant<float, 7, 4, 2, 2, 4>(), variant<float, 7, 4, 2, 1, 4>(), variant<float, 7, 3, 2, 2, 4>(), variant<float, 7, 4, 1, 2, 4>(), variant<float, 7, 4, 2, 2, 1>(), variant<float, 7, 3, 2, 2, 1>(), variant<float, 7, 4, 2, 3, 1, 1>(),
-    variant<float, 8, 4, 1, 3, 1, 0, 0, 1, 1>(), variant<float, 8, 4, 1, 3, 1>(), variant<float, 8, 4, 1, 3, 4, 0, 0, 1, 1>(), variant<float, 8, 4, 2, 3, 4, 0, 0, 1, 1>(), variant<float, 8, 4, 1, 2, 1>(), variant<float, 8, 4, 1, 2, 4>(), variant<float, 8, 4, 2, 2, 4>(), variant<float, 8, 4, 2, 1, 4>(), variant<float, 8, 3, 2, 2, 4>(), variant<float, 8, 3, 2, 2, 1>(), variant<float, 8, 4, 1, 2, 1, 1>(), variant<float, 8, 4, 2, 3, 4>(), variant<float, 8, 4, 1, 3, 4>(),
+    variant<float, 7, 4, 2, 5, 1, 0, 0, 1, 1>(), variant<float, 7, 4, 2, 3, 1, 0, 0, 1, 1>(), variant<float, 7, 4, 2, 3, 4, 0, 0, 1, 1>(), variant<float, 7, 4, 2, 3, 4>(), variant<float, 7, 4, 1, 3, 4, 0, 0, 1, 1>(), variant<float, 7, 4, 1, 3, 1, 0, 0, 1, 1>(), variant<float, 7, 4, 1, 3, 4>(), variant<float, 7, 4, 1, 3, 1>(), variant<float, 7, 4, 2, 2, 1, 1>(), variant<float, 7, 4, 2, 2, 4>(), variant<float, 7, 4, 2, 1, 4>(), variant<float, 7, 3, 2, 2, 4>(), variant<float, 7, 4, 1, 2, 4>(), variant<float, 7, 4, 2, 2, 1>(), variant<float, 7, 3, 2, 2, 1>(), variant<float, 7, 4, 2, 3, 1, 1>(),
+    variant<float, 8, 4, 2, 5, 1, 0, 0, 1, 1>(), variant<float, 8, 4, 2, 3, 1, 0, 0, 1, 1>(), variant<float, 8, 4, 1, 3, 1, 0, 0, 1, 1>(), variant<float, 8, 4, 1, 3, 1>(), variant<float, 8, 4, 1, 3, 4, 0, 0, 1, 1>(), variant<float, 8, 4, 2, 3, 4, 0, 0, 1, 1>(), variant<float, 8, 4, 1, 2, 1>(), variant<float, 8, 4, 1, 2, 4>(), variant<float, 8, 4, 2, 2, 4>(), variant<float, 8, 4, 2, 1, 4>(), variant<float, 8, 3, 2, 2, 4>(), variant<float, 8, 3, 2, 2, 1>(), variant<float, 8, 4, 1, 2, 1, 1>(), variant<float, 8, 4, 2, 3, 4>(), variant<float, 8, 4, 1, 3, 4>(),
 };
 extern const int kShapesF32HiCount = sizeof(kShapesF32Hi) / sizeof(Me2Variant);
 

@@ -1,6 +1,7 @@
 // Compiled amplitude-kernel shapes, float, n = 2, 3, 4:
 // variant<R, n, unrolled depth, helicities per walk, closing depth, waves per block,
-// prefetch (resident waves looping over items; default 0)>.
+// prefetch, waves per SIMD, points per lane, prefix sets> (the last four default to
+// 0, 0, 1, 0; the fields of heget_shape).
 // The first entry for each n is the default before tuning.
 #include "me2_item.hpp"
 
@@ -9,7 +10,7 @@ namespace heget {
 extern const Me2Variant kShapesF32Lo[] = {
     variant<float, 2, 2, 2, 1, 4>(), variant<float, 2, 2, 2, 2, 4>(), variant<float, 2, 2, 4, 2, 4>(), variant<float, 2, 2, 1, 2, 4>(), variant<float, 2, 2, 4, 2, 1>(), variant<float, 2, 2, 4, 2, 1, 1>(), variant<float, 2, 2, 4, 2, 4, 0, 0, 2>(),
     variant<float, 3, 3, 8, 2, 1>(), variant<float, 3, 3, 8, 2, 1, 0, 0, 2>(), variant<float, 3, 3, 4, 2, 1, 0, 0, 2>(), variant<float, 3, 3, 4, 2, 1>(), variant<float, 3, 3, 4, 2, 4>(), variant<float, 3, 3, 2, 2, 4>(), variant<float, 3, 3, 2, 1, 4>(), variant<float, 3, 3, 1, 2, 4>(), variant<float, 3, 3, 8, 2, 4>(), variant<float, 3, 3, 4, 2, 1, 1>(),
-    variant<float, 4, 4, 16, 3, 1, 0>(), variant<float, 4, 4, 16, 3, 1, 1>(), variant<float, 4, 4, 16, 3, 1, 0, 2>(), variant<float, 4, 4, 16, 4, 1, 0>(), variant<float, 4, 4, 16, 2, 1, 1>(), variant<float, 4, 4, 16, 2, 1>(), variant<float, 4, 4, 2, 2, 1>(), variant<float, 4, 4, 2, 2, 4>(), variant<float, 4, 4, 2, 1, 4>(), variant<float, 4, 3, 2, 2, 4>(), variant<float, 4, 3, 4, 2, 4>(), variant<float, 4, 4, 1, 2, 4>(), variant<float, 4, 4, 1, 2, 1>(), variant<float, 4, 4, 16, 2, 4>(), variant<float, 4, 4, 4, 2, 1>(), variant<float, 4, 4, 16, 2, 4, 1>(), variant<float, 4, 4, 16, 3, 1>(), variant<float, 4, 4, 4, 3, 1, 1>(),
+    variant<float, 4, 4, 16, 3, 1, 0>(), variant<float, 4, 4, 16, 3, 1, 1>(), variant<float, 4, 4, 16, 3, 1, 0, 2>(), variant<float, 4, 4, 16, 4, 1, 0>(), variant<float, 4, 4, 16, 5, 1, 0>(), variant<float, 4, 4, 16, 2, 1, 1>(), variant<float, 4, 4, 16, 2, 1>(), variant<float, 4, 4, 2, 2, 1>(), variant<float, 4, 4, 2, 2, 4>(), variant<float, 4, 4, 2, 1, 4>(), variant<float, 4, 3, 2, 2, 4>(), variant<float, 4, 3, 4, 2, 4>(), variant<float, 4, 4, 1, 2, 4>(), variant<float, 4, 4, 1, 2, 1>(), variant<float, 4, 4, 16, 2, 4>(), variant<float, 4, 4, 4, 2, 1>(), variant<float, 4, 4, 16, 2, 4, 1>(), variant<float, 4, 4, 16, 3, 1>(), variant<float, 4, 4, 4, 3, 1, 1>(),
 };
 extern const int kShapesF32LoCount = sizeof(kShapesF32Lo) / sizeof(Me2Variant);
 

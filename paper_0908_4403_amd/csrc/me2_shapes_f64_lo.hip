@@ -1,6 +1,7 @@
 // Compiled amplitude-kernel shapes, double, n = 2, 3, 4:
 // variant<R, n, unrolled depth, helicities per walk, closing depth, waves per block,
-// prefetch (resident waves looping over items; default 0)>.
+// prefetch, waves per SIMD, points per lane, prefix sets> (the last four default to
+// 0, 0, 1, 0; the fields of heget_shape).
 // The first entry for each n is the default before tuning.
 #include "me2_item.hpp"
 

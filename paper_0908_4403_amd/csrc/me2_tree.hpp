@@ -367,7 +367,11 @@ __device__ __forceinline__ void close_pair_wide(const PT &T, int a, int b, const
 //     G_xy = d P(q + k_x + k_y) [V_y g_x + V_x g_y],  g_x = current after x,
 // and the node closes with six products U_ab . G_xy instead of twelve.
 // CL = 3 takes each split's product in FP64 where H >= 8 (close_pair_wide);
-// CL = 4 always in the working precision, converted once into the FP64 sum.
+// CL = 4 always in the working precision, converted once into the FP64 sum;
+// CL = 5 sums the products of complementary splits, {x, y} | {a, b} and
+// {a, b} | {x, y} (the eight orderings whose first two photons form either
+// set), in the working precision and enters each such sum into the FP64
+// ordering sum once: three FP64 entries per helicity instead of six.
 template <typename R, int H, int NS, int CL, unsigned MASK, typename PT>
 __device__ __forceinline__ void quad_close(const Slots<R, H, NS> &S, const PT &T, const Chain<R, H> &c,
                                            const LMom<R> &q, Acc<H> &acc)
@@ -386,24 +390,62 @@ __device__ __forceinline__ void quad_close(const Slots<R, H, NS> &S, const PT &T
         const Prop<R> P = propagate<R>(q, S.k[sl[i]], q1[i]);
         update<R, H>(S.v[sl[i]], c, P, g1[i]);
     }
-    // (x, y) index pairs into sl and the closing pair (a, b) of the other two
+    // (x, y) index pairs into sl and the closing pair (a, b) of the other two;
+    // split 5 - t is the complement of split t
     constexpr int X[6] = {0, 0, 0, 1, 1, 2}, Y[6] = {1, 2, 3, 2, 3, 3};
     constexpr int A[6] = {2, 1, 1, 0, 0, 0}, B[6] = {3, 3, 2, 3, 2, 1};
-#pragma unroll
-    for (int t = 0; t < 6; ++t) {
+    // G_xy of split t
+    auto split_current = [&](int t) {
         LMom<R> q2;
         const Prop<R> P = propagate<R>(q1[X[t]], S.k[sl[Y[t]]], q2);
         Half<R, H> s = vertex_half<R, H>(S.v[sl[Y[t]]], g1[X[t]]);
         vertex_half_add<R, H>(S.v[sl[X[t]]], g1[Y[t]], s);
         Chain<R, H> g2;
         propagator_half<R, H>(P, s, g2);
-        // FP64 products pay off where a split's conversions are shared by
-        // many configurations and FP64 issues as fast as FP32 (and always in
-        // FP64, where there are none)
-        if constexpr (std::is_same<R, double>::value || (H >= 8 && CL == 3))
-            close_pair_wide<R, H>(T, sl[A[t]], sl[B[t]], g2, acc);
-        else
-            close_pair<R, H>(T, sl[A[t]], sl[B[t]], g2, acc);
+        return g2;
+    };
+    if constexpr (CL == 5 && !std::is_same<R, double>::value) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const Chain<R, H> ga = split_current(t);
+            const Chain<R, H> gb = split_current(5 - t);
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                R u1r, u1i, u2r, u2i, v1r, v1i, v2r, v2i;
+                T.get(sl[A[t]], sl[B[t]], h, u1r, u1i, u2r, u2i);
+                T.get(sl[A[5 - t]], sl[B[5 - t]], h, v1r, v1i, v2r, v2i);
+                R ar = u1r * ga.g2r[h];
+                ar = fma(-u1i, ga.g2i[h], ar);
+                ar = fma(u2r, ga.g3r[h], ar);
+                ar = fma(-u2i, ga.g3i[h], ar);
+                ar = fma(v1r, gb.g2r[h], ar);
+                ar = fma(-v1i, gb.g2i[h], ar);
+                ar = fma(v2r, gb.g3r[h], ar);
+                ar = fma(-v2i, gb.g3i[h], ar);
+                R ai = u1r * ga.g2i[h];
+                ai = fma(u1i, ga.g2r[h], ai);
+                ai = fma(u2r, ga.g3i[h], ai);
+                ai = fma(u2i, ga.g3r[h], ai);
+                ai = fma(v1r, gb.g2i[h], ai);
+                ai = fma(v1i, gb.g2r[h], ai);
+                ai = fma(v2r, gb.g3i[h], ai);
+                ai = fma(v2i, gb.g3r[h], ai);
+                acc.re[h] += static_cast<double>(ar);
+                acc.im[h] += static_cast<double>(ai);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            const Chain<R, H> g2 = split_current(t);
+            // FP64 products pay off where a split's conversions are shared by
+            // many configurations and FP64 issues as fast as FP32 (and always in
+            // FP64, where there are none)
+            if constexpr (std::is_same<R, double>::value || (H >= 8 && CL == 3))
+                close_pair_wide<R, H>(T, sl[A[t]], sl[B[t]], g2, acc);
+            else
+                close_pair<R, H>(T, sl[A[t]], sl[B[t]], g2, acc);
+        }
     }
 }
 
@@ -431,7 +473,7 @@ __device__ __forceinline__ void close_pair_wide(const PT &T, int a, int b, const
 
 // Unrolled subtree over the slot photons in MASK, entered with current c at
 // momentum q.  CL = 1 closes photon by photon; CL = 2 closes the last pair;
-// CL = 3 and 4 close the last four photons with pair sums at both ends.
+// CL = 3, 4 and 5 close the last four photons with pair sums at both ends.
 template <typename R, int H, int NS, int CL, unsigned MASK, typename PT>
 __device__ __forceinline__ void subtree(const Slots<R, H, NS> &S, const PT &T, const Chain<R, H> &c,
                                         const LMom<R> &q, Acc<H> &acc)
