@@ -290,7 +290,12 @@ heget_status heget_timing_read(double *me2_ms, int64_t *me2_launches, int reset)
  *                        currents of all orderings of a set (subset recursion)
  *                        before the subtree, which then runs once per set --
  *                        the current reuse of the MadGraph program carried to
- *                        the meeting point of the two ends (Appendix A.1) */
+ *                        the meeting point of the two ends (Appendix A.1);
+ *                        2 (with unrolled = n): meet in the middle -- subset
+ *                        currents from the v-bar end for every set of up to
+ *                        K = (n + 1) / 2 photons, subset currents from the u
+ *                        end for the other side, one contraction per set of
+ *                        K photons (closing is then unused) */
 typedef struct {
     int32_t unrolled, helicities_per_walk, closing, waves_per_block, prefetch, waves_per_simd,
         points_per_lane, prefix_sets;

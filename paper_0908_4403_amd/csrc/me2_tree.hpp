@@ -113,7 +113,9 @@ struct Slots {
 struct NoPairs {};
 
 // V'(lam) of photon j for the H variants whose helicity configurations are
-// cfg0 .. cfg0+H-1 (bit j set = helicity +1).  cfg0 is wave-uniform.
+// cfg0 .. cfg0+H-1 (bit j set = helicity +1).  cfg0 is wave-uniform and a
+// multiple of H, so configuration cfg0 + h is cfg0 | h: written so, a photon
+// at or above log2(H) visibly has one block for all H variants.
 template <typename R, int H>
 __device__ __forceinline__ Vert<R, H> make_vert(const LMom<R> &k, uint32_t cfg0, int j)
 {
@@ -122,7 +124,7 @@ __device__ __forceinline__ Vert<R, H> make_vert(const LMom<R> &k, uint32_t cfg0,
     const R xm = k.x * k.im, ym = k.y * k.im;  // kappa / k-
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-        const bool plus = ((cfg0 + h) >> j) & 1u;
+        const bool plus = ((cfg0 | static_cast<uint32_t>(h)) >> j) & 1u;
         v.br[h] = plus ? -xm : xp;
         v.bi[h] = plus ? -ym : yp;
         v.gr[h] = plus ? xp : -xm;
@@ -645,6 +647,196 @@ __device__ __forceinline__ void prefix_sets(const R *tab, int lane, uint32_t cfg
     }
 }
 
+// Row vector of the u end (a current flowing towards the u spinor) for H
+// variants: (r1, r2) complex, contracted with a v-bar-end current g as
+// r1 g2 + r2 g3.
+template <typename R, int H>
+struct Row {
+    R r1r[H], r1i[H], r2r[H], r2i[H];
+};
+
+// s = r V' for every variant (V' = [[1, beta], [gamma, -1]]), started or added.
+template <typename R, int H>
+__device__ __forceinline__ Half<R, H> row_vertex(const Vert<R, H> &v, const Row<R, H> &r)
+{
+    Half<R, H> s;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        s.s1r[h] = fma(v.gr[h], r.r2r[h], fma(-v.gi[h], r.r2i[h], r.r1r[h]));
+        s.s1i[h] = fma(v.gr[h], r.r2i[h], fma(v.gi[h], r.r2r[h], r.r1i[h]));
+        s.s2r[h] = fma(v.br[h], r.r1r[h], fma(-v.bi[h], r.r1i[h], -r.r2r[h]));
+        s.s2i[h] = fma(v.br[h], r.r1i[h], fma(v.bi[h], r.r1r[h], -r.r2i[h]));
+    }
+    return s;
+}
+
+template <typename R, int H>
+__device__ __forceinline__ void row_vertex_add(const Vert<R, H> &v, const Row<R, H> &r, Half<R, H> &s)
+{
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        s.s1r[h] = fma(v.gr[h], r.r2r[h], fma(-v.gi[h], r.r2i[h], s.s1r[h] + r.r1r[h]));
+        s.s1i[h] = fma(v.gr[h], r.r2i[h], fma(v.gi[h], r.r2r[h], s.s1i[h] + r.r1i[h]));
+        s.s2r[h] = fma(v.br[h], r.r1r[h], fma(-v.bi[h], r.r1i[h], s.s2r[h] - r.r2r[h]));
+        s.s2i[h] = fma(v.br[h], r.r1i[h], fma(v.bi[h], r.r1r[h], s.s2i[h] - r.r2i[h]));
+    }
+}
+
+// r' = s d P(q) for a row: P(q) = [[q-, -(qx + i qy)], [-(qx - i qy), q+]]
+// acts from the right.
+template <typename R, int H>
+__device__ __forceinline__ void row_propagator(const Prop<R> &P, const Half<R, H> &s, Row<R, H> &o)
+{
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        o.r1r[h] = P.m * s.s1r[h] - P.x * s.s2r[h] - P.y * s.s2i[h];
+        o.r1i[h] = P.m * s.s1i[h] - P.x * s.s2i[h] + P.y * s.s2r[h];
+        o.r2r[h] = P.p * s.s2r[h] - P.x * s.s1r[h] + P.y * s.s1i[h];
+        o.r2i[h] = P.p * s.s2i[h] - P.x * s.s1i[h] - P.y * s.s1r[h];
+    }
+}
+
+// Meet in the middle (shape field prefix_sets = 2; the whole tree unrolled,
+// photons in registers).  Every ordering of the n photons splits uniquely into
+// the set A of its first K photons (from the v-bar end) and the set B of the
+// other n - K, and its amplitude factorises at the propagator between them:
+// the v-bar-end current after A times the u-end row vector arriving from B.
+// Summed over the orderings of A and of B,
+//     sum over all orderings = sum over |A| = K of W(B) . J(A),
+//     J(Q) = d(q_Q) P(q_Q) sum_{j in Q} V_j J(Q \ j),  q_Q = -p2 + sum_Q k,
+//     R(C) = [sum_{c in C} R(C \ c) V_c] d(p1 - sum_C k) P(p1 - sum_C k),
+//     W(B) = sum_{b in B} R(B \ b) V_b,
+// with J(empty) the v-bar spinor and R(empty) V_c = (gamma_c, -1) the u-end
+// closing vertex.  This is the two-sided current reuse of the MadGraph program
+// (Appendix A.1) taken to the middle of every chain: each subset current is
+// formed once per helicity walk instead of once per ordering prefix.  The
+// C(n, K) contractions W(B) . J(A) are taken in the working precision and
+// each enters the FP64 ordering sum.  Levels up to K - 1 (v-bar end) and
+// n - K - 1 (u end) are held; level K and the row vectors W are formed at the
+// contraction that uses them.
+// Momentum base + SIGN * sum of the photons in MASK (in increasing photon order).
+template <int SIGN, unsigned MASK, typename R, int H, int N>
+__device__ __forceinline__ LMom<R> set_momentum(const LMom<R> &base, const Slots<R, H, N> &S)
+{
+    LMom<R> q = {base.p, base.m, base.x, base.y, R(0), R(0)};
+    for_each_bit<MASK>([&](auto bit) {
+        constexpr int b = decltype(bit)::value;
+        if constexpr (SIGN > 0) {
+            q.p += S.k[b].p, q.m += S.k[b].m, q.x += S.k[b].x, q.y += S.k[b].y;
+        } else {
+            q.p -= S.k[b].p, q.m -= S.k[b].m, q.x -= S.k[b].x, q.y -= S.k[b].y;
+        }
+    });
+    return q;
+}
+
+// Compile-time loop over the masks of n bits with L bits set, in increasing order.
+template <int N, int L, typename F>
+__device__ __forceinline__ void for_each_subset(F &&f)
+{
+    static_for<1, (1 << N)>([&](auto mi) {
+        constexpr uint32_t mask = decltype(mi)::value;
+        if constexpr (__builtin_popcount(mask) == L) f(std::integral_constant<uint32_t, mask>{});
+    });
+}
+
+template <typename R, int N, int K, int H>
+__device__ __forceinline__ void meet_sets(const Slots<R, H, N> &S, const LMom<R> &p1, const LMom<R> &q0,
+                                          Acc<H> &acc)
+{
+    static_assert(K >= 2 && N - K >= 2, "both ends need at least two photons");
+    constexpr uint32_t kAll = (1u << N) - 1u;
+    constexpr int kU = N - K;
+    Chain<R, H> J[1 << N];
+    Row<R, H> Rw[1 << N];
+    // v-bar end, level by level (a level's currents die once the next is formed)
+    static_for<1, K>([&](auto li) {
+        constexpr int L = decltype(li)::value;
+        for_each_subset<N, L>([&](auto mi) {
+            constexpr uint32_t mask = decltype(mi)::value;
+            constexpr int low = __builtin_ctz(mask);
+            const Prop<R> P = prop_at<R>(set_momentum<1, mask>(q0, S));
+            if constexpr (L == 1) {
+                // V (1, 0) = (1, gamma)
+                const Vert<R, H> &v = S.v[low];
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    J[mask].g2r[h] = fma(-P.x, v.gr[h], fma(P.y, v.gi[h], P.m));
+                    J[mask].g2i[h] = -fma(P.x, v.gi[h], P.y * v.gr[h]);
+                    J[mask].g3r[h] = fma(P.p, v.gr[h], -P.x);
+                    J[mask].g3i[h] = fma(P.p, v.gi[h], P.y);
+                }
+            } else {
+                Half<R, H> sl = vertex_half<R, H>(S.v[low], J[mask & ~(1u << low)]);
+                for_each_bit<(mask & (mask - 1u))>([&](auto bit) {
+                    constexpr int b = decltype(bit)::value;
+                    vertex_half_add<R, H>(S.v[b], J[mask & ~(1u << b)], sl);
+                });
+                propagator_half<R, H>(P, sl, J[mask]);
+            }
+        });
+    });
+    // u end, levels 1 .. n - K - 1
+    static_for<1, kU>([&](auto li) {
+        constexpr int L = decltype(li)::value;
+        for_each_subset<N, L>([&](auto mi) {
+            constexpr uint32_t mask = decltype(mi)::value;
+            constexpr int low = __builtin_ctz(mask);
+            const Prop<R> P = prop_at<R>(set_momentum<-1, mask>(p1, S));
+            if constexpr (L == 1) {
+                // (gamma, -1) d P(p1 - k): the u-end current after one photon
+                const Vert<R, H> &v = S.v[low];
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    Rw[mask].r1r[h] = fma(v.gr[h], P.m, P.x);
+                    Rw[mask].r1i[h] = fma(v.gi[h], P.m, -P.y);
+                    Rw[mask].r2r[h] = -fma(v.gr[h], P.x, fma(-v.gi[h], P.y, P.p));
+                    Rw[mask].r2i[h] = -fma(v.gr[h], P.y, v.gi[h] * P.x);
+                }
+            } else {
+                Half<R, H> sl = row_vertex<R, H>(S.v[low], Rw[mask & ~(1u << low)]);
+                for_each_bit<(mask & (mask - 1u))>([&](auto bit) {
+                    constexpr int b = decltype(bit)::value;
+                    row_vertex_add<R, H>(S.v[b], Rw[mask & ~(1u << b)], sl);
+                });
+                row_propagator<R, H>(P, sl, Rw[mask]);
+            }
+        });
+    });
+    // the contractions, one per set A of K photons
+    for_each_subset<N, K>([&](auto mi) {
+        constexpr uint32_t A = decltype(mi)::value;
+        constexpr uint32_t B = kAll & ~A;
+        constexpr int low = __builtin_ctz(A);
+        Half<R, H> sl = vertex_half<R, H>(S.v[low], J[A & ~(1u << low)]);
+        for_each_bit<(A & (A - 1u))>([&](auto bit) {
+            constexpr int b = decltype(bit)::value;
+            vertex_half_add<R, H>(S.v[b], J[A & ~(1u << b)], sl);
+        });
+        Chain<R, H> ja;
+        propagator_half<R, H>(prop_at<R>(set_momentum<1, A>(q0, S)), sl, ja);
+        constexpr int lowb = __builtin_ctz(B);
+        Half<R, H> w = row_vertex<R, H>(S.v[lowb], Rw[B & ~(1u << lowb)]);
+        for_each_bit<(B & (B - 1u))>([&](auto bit) {
+            constexpr int b = decltype(bit)::value;
+            row_vertex_add<R, H>(S.v[b], Rw[B & ~(1u << b)], w);
+        });
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            R ar = w.s1r[h] * ja.g2r[h];
+            ar = fma(-w.s1i[h], ja.g2i[h], ar);
+            ar = fma(w.s2r[h], ja.g3r[h], ar);
+            ar = fma(-w.s2i[h], ja.g3i[h], ar);
+            R ai = w.s1r[h] * ja.g2i[h];
+            ai = fma(w.s1i[h], ja.g2r[h], ai);
+            ai = fma(w.s2r[h], ja.g3i[h], ai);
+            ai = fma(w.s2i[h], ja.g3r[h], ai);
+            acc.re[h] += static_cast<double>(ar);
+            acc.im[h] += static_cast<double>(ai);
+        }
+    });
+}
+
 // Per-point inputs after the FP64 set-up.
 template <typename R, int N>
 struct PointIn {
@@ -676,7 +868,16 @@ __device__ __forceinline__ double tree_sum(const PointIn<R, N> &in, R *tab, int 
             acc.re[h] = 0.0;
             acc.im[h] = 0.0;
         }
-        if constexpr (N <= MB) {
+        if constexpr (PS == 2) {
+            static_assert(N <= MB, "meeting in the middle keeps every photon in registers");
+            Slots<R, H, N> S;
+#pragma unroll
+            for (int s = 0; s < N; ++s) {
+                S.k[s] = in.k[s];
+                S.v[s] = make_vert<R, H>(in.k[s], cfg0, s);
+            }
+            meet_sets<R, N, (N + 1) / 2, H>(S, in.p1, in.q0, acc);
+        } else if constexpr (N <= MB) {
             Slots<R, H, N> S;
 #pragma unroll
             for (int s = 0; s < N; ++s) {

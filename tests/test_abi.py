@@ -165,6 +165,28 @@ def _flops_prefix_sets(n, mb, h, cl):
     return walk * 2 ** n // h
 
 
+def _flops_meet(n, h):
+    """Closed form for meeting in the middle with nothing shared (h = 1): with
+    K = (n + 1) / 2, the v-bar-end subset currents of every set of 1 .. K - 1
+    photons, the u-end ones of every set of 1 .. n - K - 1, and per set of K
+    photons its current, the row vector of the other n - K photons and one
+    contraction.  A node of m photons: momentum 4m + 10; per helicity 11 for
+    one photon, else 36 + 20 (m - 1).  Row vector: 16 + 20 (n - K - 1) per
+    helicity; contraction 16 per helicity; vertex blocks 4 per photon."""
+    import math
+    K = (n + 1) // 2
+    ku = n - K
+
+    def node(m):
+        return 4 * m + 10 + (11 if m == 1 else 36 + 20 * (m - 1)) * h
+
+    walk = 4 * n + 4 * h
+    walk += sum(math.comb(n, m) * node(m) for m in range(1, K))
+    walk += sum(math.comb(n, m) * node(m) for m in range(1, ku))
+    walk += math.comb(n, K) * (node(K) + (16 + 20 * (ku - 1)) * h + 16 * h)
+    return walk * 2 ** n // h
+
+
 def test_flop_count_of_every_shape():
     """heget_me2_flops equals the closed form where nothing is shared (h = 1, or
     photons in run-time slots), and is below it where helicities share values."""
@@ -177,6 +199,11 @@ def test_flop_count_of_every_shape():
                     f, got = H.me2_flops(n, prec)
                     assert got == shape
                     mb, h, cl, wpb, pf, wpe, ppl, ps = shape
+                    if ps == 2:
+                        assert mb == n, (n, shape)
+                        ref = _flops_meet(n, h)
+                        assert (f == ref) if h == 1 else (0.25 * ref < f < ref), (n, shape, f, ref)
+                        continue
                     if ps == 1 and n - mb >= 2:
                         assert f == _flops_prefix_sets(n, mb, h, cl), (n, shape, f)
                         continue
