@@ -295,7 +295,11 @@ heget_status heget_timing_read(double *me2_ms, int64_t *me2_launches, int reset)
  *                        currents from the v-bar end for every set of up to
  *                        K = (n + 1) / 2 photons, subset currents from the u
  *                        end for the other side, one contraction per set of
- *                        K photons (closing is then unused) */
+ *                        K photons (closing is then unused), with the
+ *                        momentum part of the nodes formed once per point;
+ *                        3: as 2 with it formed per helicity walk (fewer
+ *                        values held, for n >= 7); 4: as 3 with the v-bar-end
+ *                        currents of K - 1 photons held in LDS */
 typedef struct {
     int32_t unrolled, helicities_per_walk, closing, waves_per_block, prefetch, waves_per_simd,
         points_per_lane, prefix_sets;

@@ -476,7 +476,7 @@ double me2_flops_per_point(int n, int mb, int h, int cl, int ps)
     w.cl = cl;
     w.shared = n <= mb;
     const int k = n - mb;
-    if (ps == 2) {
+    if (ps >= 2) {
         // meeting in the middle (whole tree unrolled, so values that do not
         // depend on a variant photon are shared): v-bar-end currents of every
         // set of up to K = (n + 1) / 2 photons, u-end row vectors of every set
@@ -485,12 +485,16 @@ double me2_flops_per_point(int n, int mb, int h, int cl, int ps)
         // 4L (sum of its photons) + q^2 5 + 1/q^2 1 + scale 4; per distinct
         // value one photon 11, else a vertex half 16, L - 1 vertex halves
         // added 20 each and a propagator half 20.  W: 16 + 20 (n - K - 1) per
-        // distinct value; contraction 14 + 2 FP64 adds per helicity.
+        // distinct value; contraction 14 + 2 FP64 adds per helicity.  With
+        // ps = 2 the momentum parts are formed once per point (the compiler
+        // takes them out of the loop over walks), otherwise once per walk.
         const int K = (n + 1) / 2, ku = n - K;
+        double momenta = 0.0;
         auto node = [&](unsigned set) {
             const int L = __builtin_popcount(set);
             const double per = L == 1 ? 11.0 : 36.0 + 20.0 * (L - 1);
-            return 4.0 * L + 10.0 + per * w.var_count(set);
+            momenta += 4.0 * L + 10.0;
+            return per * w.var_count(set);
         };
         w.total += 4.0 * n;
         for (unsigned set = 1; set < (1u << n); ++set) {
@@ -502,6 +506,9 @@ double me2_flops_per_point(int n, int mb, int h, int cl, int ps)
                 w.total += node(set) + (16.0 + 20.0 * (ku - 1)) * w.var_count(rest) + 16.0 * h;
             }
         }
+        w.total += 4.0 * h;
+        const double walks = double(1 << n) / double(h);
+        return w.total * walks + momenta * (ps == 2 ? 1.0 : walks);
     } else if (ps == 1 && k >= 2) {
         // prefix sets: per k-subset of the photons, its vertex blocks and the
         // subset recursion over its subsets Q (momentum part 14, a vertex half

@@ -22,7 +22,9 @@ struct Me2Variant {
     int pf;     // 1: resident waves loop over the items, loading the next one ahead
     int wpe;    // minimum waves per SIMD the kernel is compiled for (0: no bound)
     int ppl;    // points per lane: 64-point tiles per work item (1 unless pf = 0)
-    int ps;     // 1: top levels walked by prefix sets (currents summed over their orderings)
+    int ps;     // 1: top levels walked by prefix sets (currents summed over their orderings);
+                // 2-4: meet in the middle (2: momenta once per point, 3: per walk,
+                // 4: per walk with the held v-bar-end currents in LDS)
     const void *func;  // kernel symbol
 };
 

@@ -182,8 +182,10 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
            double *__restrict__ wout, unsigned *__restrict__ flags)
 {
     static_assert(PPL == 1 || PF == 0, "several points per lane only without prefetch");
-    constexpr int kTab = N > MB ? kPhotonFields * N * 64 : 0;  // LDS photon table of one walk
-    __shared__ R tab_all[N > MB ? WPB * PPL * kTab : 1];
+    // LDS of one walk: the photon table of the top levels, or the held
+    // currents of the meeting in the middle with LDS staging (PS = 4)
+    constexpr int kTab = N > MB ? kPhotonFields * N * 64 : PS == 4 ? meet_lds_values<N, H>() * 64 : 0;
+    __shared__ R tab_all[kTab > 0 ? WPB * PPL * kTab : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t npts = d_count ? *d_count : count;
@@ -206,7 +208,7 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
         end = (x + 1) * per < nitems ? (x + 1) * per : nitems;
     }
     if (item >= end) return;  // whole wave
-    R *tab = tab_all + (N > MB ? wave * PPL * kTab : 0);
+    R *tab = tab_all + wave * PPL * kTab;
     const double *wf = partials && nchunks == 1 ? wfac : nullptr;
     const uint16_t *hl = H == 0 ? hel : nullptr;
     auto tile_of = [nchunks](int64_t it) -> int64_t { return nchunks == 1 ? it : it / nchunks; };

@@ -10,9 +10,11 @@
 namespace heget {
 
 // Tables defined in the me2_shapes_*.hip translation units.
-extern const Me2Variant kShapesF32Lo[], kShapesF32Mid[], kShapesF32Hi[];
+extern const Me2Variant kShapesF32Lo[], kShapesF32Mid[], kShapesF32Meet7[], kShapesF32Meet8[],
+    kShapesF32Hi[];
 extern const Me2Variant kShapesF64Lo[], kShapesF64Mid[], kShapesF64Hi[];
-extern const int kShapesF32LoCount, kShapesF32MidCount, kShapesF32HiCount;
+extern const int kShapesF32LoCount, kShapesF32MidCount, kShapesF32Meet7Count, kShapesF32Meet8Count,
+    kShapesF32HiCount;
 extern const int kShapesF64LoCount, kShapesF64MidCount, kShapesF64HiCount;
 extern const Me2Variant kShapesSampled[];
 extern const int kShapesSampledCount;
@@ -21,11 +23,14 @@ static const std::vector<Me2Variant> &all_variants()
 {
     static const std::vector<Me2Variant> v = [] {
         std::vector<Me2Variant> r;
-        const Me2Variant *tabs[] = {kShapesF32Lo, kShapesF32Mid, kShapesF32Hi,
-                                    kShapesF64Lo, kShapesF64Mid, kShapesF64Hi};
-        const int counts[] = {kShapesF32LoCount, kShapesF32MidCount, kShapesF32HiCount,
-                              kShapesF64LoCount, kShapesF64MidCount, kShapesF64HiCount};
-        for (int t = 0; t < 6; ++t)
+        // the meeting-in-the-middle tables come before the other n = 7, 8
+        // shapes: their first entries are the defaults
+        const Me2Variant *tabs[] = {kShapesF32Lo, kShapesF32Mid, kShapesF32Meet7, kShapesF32Meet8,
+                                    kShapesF32Hi, kShapesF64Lo, kShapesF64Mid, kShapesF64Hi};
+        const int counts[] = {kShapesF32LoCount, kShapesF32MidCount, kShapesF32Meet7Count,
+                              kShapesF32Meet8Count, kShapesF32HiCount, kShapesF64LoCount,
+                              kShapesF64MidCount, kShapesF64HiCount};
+        for (int t = 0; t < 8; ++t)
             for (int i = 0; i < counts[t]; ++i) r.push_back(tabs[t][i]);
         return r;
     }();

@@ -8,7 +8,7 @@
 namespace heget {
 
 extern const Me2Variant kShapesF64Hi[] = {
-    variant<double, 7, 4, 2, 3, 1, 1, 0, 1, 1>(), variant<double, 7, 4, 1, 3, 1, 0, 0, 1, 1>(), variant<double, 7, 4, 1, 3, 1, 1>(), variant<double, 7, 4, 1, 3, 1, 1, 0, 1, 1>(), variant<double, 7, 4, 1, 2, 4>(), variant<double, 7, 4, 1, 1, 4>(), variant<double, 7, 3, 1, 2, 4>(), variant<double, 7, 3, 2, 2, 4>(), variant<double, 7, 4, 1, 2, 1>(), variant<double, 7, 4, 1, 2, 1, 1>(),
+    variant<double, 7, 7, 1, 2, 1, 0, 0, 1, 3>(), variant<double, 7, 4, 2, 3, 1, 1, 0, 1, 1>(), variant<double, 7, 4, 1, 3, 1, 0, 0, 1, 1>(), variant<double, 7, 4, 1, 3, 1, 1>(), variant<double, 7, 4, 1, 3, 1, 1, 0, 1, 1>(), variant<double, 7, 4, 1, 2, 4>(), variant<double, 7, 4, 1, 1, 4>(), variant<double, 7, 3, 1, 2, 4>(), variant<double, 7, 3, 2, 2, 4>(), variant<double, 7, 4, 1, 2, 1>(), variant<double, 7, 4, 1, 2, 1, 1>(),
     variant<double, 8, 4, 2, 3, 1, 1, 0, 1, 1>(), variant<double, 8, 4, 1, 3, 1, 0, 0, 1, 1>(), variant<double, 8, 4, 1, 3, 1, 1>(), variant<double, 8, 4, 1, 3, 1, 1, 0, 1, 1>(), variant<double, 8, 4, 1, 2, 4>(), variant<double, 8, 4, 1, 1, 4>(), variant<double, 8, 3, 1, 2, 4>(), variant<double, 8, 3, 2, 2, 4>(), variant<double, 8, 4, 1, 2, 1>(), variant<double, 8, 4, 1, 2, 1, 1>(),
 };
 extern const int kShapesF64HiCount = sizeof(kShapesF64Hi) / sizeof(Me2Variant);

@@ -740,15 +740,78 @@ __device__ __forceinline__ void for_each_subset(F &&f)
     });
 }
 
-template <typename R, int N, int K, int H>
+// Rank of MASK among the n-bit masks with as many bits set (increasing order).
+template <int N>
+constexpr int subset_rank(uint32_t mask)
+{
+    int r = 0;
+    for (uint32_t m = 1; m < mask; ++m) r += __builtin_popcount(m) == __builtin_popcount(mask);
+    return r;
+}
+
+constexpr int binomial(int n, int k)
+{
+    int r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+// LDS values per lane of meet_sets with LDS staging: the v-bar-end currents of
+// level K - 1, 4 H components each.
+template <int N, int H>
+constexpr int meet_lds_values()
+{
+    return binomial(N, (N + 1) / 2 - 1) * 4 * H;
+}
+
+// Level-(K - 1) current of set MASK in the wave's LDS region:
+// [rank][component][lane], component c of variant h at 4 h + c.
+template <typename R, int N, int H, uint32_t MASK>
+__device__ __forceinline__ void lds_put(R *lds, int lane, const Chain<R, H> &c)
+{
+    R *b = lds + subset_rank<N>(MASK) * 4 * H * 64 + lane;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        b[(4 * h + 0) * 64] = c.g2r[h];
+        b[(4 * h + 1) * 64] = c.g2i[h];
+        b[(4 * h + 2) * 64] = c.g3r[h];
+        b[(4 * h + 3) * 64] = c.g3i[h];
+    }
+}
+
+template <typename R, int N, int H, uint32_t MASK>
+__device__ __forceinline__ Chain<R, H> lds_get(const R *lds, int lane)
+{
+    const R *b = lds + subset_rank<N>(MASK) * 4 * H * 64 + lane;
+    Chain<R, H> c;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        c.g2r[h] = b[(4 * h + 0) * 64];
+        c.g2i[h] = b[(4 * h + 1) * 64];
+        c.g3r[h] = b[(4 * h + 2) * 64];
+        c.g3i[h] = b[(4 * h + 3) * 64];
+    }
+    return c;
+}
+
+// With kLds the v-bar-end currents of level K - 1 go to the wave's LDS region
+// `lds` (meet_lds_values<N, H>() values per lane) instead of registers, for
+// the shapes whose held currents would not fit in registers.
+template <typename R, int N, int K, int H, bool kLds = false>
 __device__ __forceinline__ void meet_sets(const Slots<R, H, N> &S, const LMom<R> &p1, const LMom<R> &q0,
-                                          Acc<H> &acc)
+                                          Acc<H> &acc, R *lds = nullptr, int lane = 0)
 {
     static_assert(K >= 2 && N - K >= 2, "both ends need at least two photons");
     constexpr uint32_t kAll = (1u << N) - 1u;
     constexpr int kU = N - K;
     Chain<R, H> J[1 << N];
     Row<R, H> Rw[1 << N];
+    // current of set M of level K - 1 (registers or LDS)
+    auto held = [&](auto mi) -> Chain<R, H> {
+        constexpr uint32_t M = decltype(mi)::value;
+        if constexpr (kLds && __builtin_popcount(M) == K - 1) return lds_get<R, N, H, M>(lds, lane);
+        else return J[M];
+    };
     // v-bar end, level by level (a level's currents die once the next is formed)
     static_for<1, K>([&](auto li) {
         constexpr int L = decltype(li)::value;
@@ -773,7 +836,9 @@ __device__ __forceinline__ void meet_sets(const Slots<R, H, N> &S, const LMom<R>
                     vertex_half_add<R, H>(S.v[b], J[mask & ~(1u << b)], sl);
                 });
                 propagator_half<R, H>(P, sl, J[mask]);
+                if constexpr (kLds && L == K - 1) lds_put<R, N, H, mask>(lds, lane, J[mask]);
             }
+            if constexpr (kLds) __builtin_amdgcn_sched_barrier(0);
         });
     });
     // u end, levels 1 .. n - K - 1
@@ -801,6 +866,7 @@ __device__ __forceinline__ void meet_sets(const Slots<R, H, N> &S, const LMom<R>
                 });
                 row_propagator<R, H>(P, sl, Rw[mask]);
             }
+            if constexpr (kLds) __builtin_amdgcn_sched_barrier(0);
         });
     });
     // the contractions, one per set A of K photons
@@ -808,10 +874,10 @@ __device__ __forceinline__ void meet_sets(const Slots<R, H, N> &S, const LMom<R>
         constexpr uint32_t A = decltype(mi)::value;
         constexpr uint32_t B = kAll & ~A;
         constexpr int low = __builtin_ctz(A);
-        Half<R, H> sl = vertex_half<R, H>(S.v[low], J[A & ~(1u << low)]);
+        Half<R, H> sl = vertex_half<R, H>(S.v[low], held(std::integral_constant<uint32_t, (A & ~(1u << low))>{}));
         for_each_bit<(A & (A - 1u))>([&](auto bit) {
             constexpr int b = decltype(bit)::value;
-            vertex_half_add<R, H>(S.v[b], J[A & ~(1u << b)], sl);
+            vertex_half_add<R, H>(S.v[b], held(std::integral_constant<uint32_t, (A & ~(1u << b))>{}), sl);
         });
         Chain<R, H> ja;
         propagator_half<R, H>(prop_at<R>(set_momentum<1, A>(q0, S)), sl, ja);
@@ -834,6 +900,10 @@ __device__ __forceinline__ void meet_sets(const Slots<R, H, N> &S, const LMom<R>
             acc.re[h] += static_cast<double>(ar);
             acc.im[h] += static_cast<double>(ai);
         }
+        // with LDS staging, no instruction moves across a node or contraction
+        // (the scheduler would otherwise hoist later nodes' loads and products
+        // and hold their values together)
+        if constexpr (kLds) __builtin_amdgcn_sched_barrier(0);
     });
 }
 
@@ -868,15 +938,26 @@ __device__ __forceinline__ double tree_sum(const PointIn<R, N> &in, R *tab, int 
             acc.re[h] = 0.0;
             acc.im[h] = 0.0;
         }
-        if constexpr (PS == 2) {
+        if constexpr (PS >= 2) {
             static_assert(N <= MB, "meeting in the middle keeps every photon in registers");
+            // PS = 2 leaves it to the compiler where the momentum part of the
+            // nodes (the same in every pass) is formed: it hoists it out of
+            // the pass loop and holds all of it across.  PS = 3 and 4 hide the
+            // momenta behind empty asm statements, so that part is formed per
+            // pass next to its use (for walks whose held values would
+            // otherwise not fit in registers); PS = 4 also holds the v-bar-end
+            // currents of level K - 1 in LDS.
             Slots<R, H, N> S;
+            LMom<R> p1 = in.p1, q0 = in.q0;
 #pragma unroll
             for (int s = 0; s < N; ++s) {
                 S.k[s] = in.k[s];
+                if constexpr (PS >= 3)
+                    asm volatile("" : "+v"(S.k[s].p), "+v"(S.k[s].m), "+v"(S.k[s].x), "+v"(S.k[s].y));
                 S.v[s] = make_vert<R, H>(in.k[s], cfg0, s);
             }
-            meet_sets<R, N, (N + 1) / 2, H>(S, in.p1, in.q0, acc);
+            if constexpr (PS >= 3) asm volatile("" : "+v"(p1.p), "+v"(p1.m), "+v"(q0.p), "+v"(q0.m));
+            meet_sets<R, N, (N + 1) / 2, H, PS == 4>(S, p1, q0, acc, tab, lane);
         } else if constexpr (N <= MB) {
             Slots<R, H, N> S;
 #pragma unroll
