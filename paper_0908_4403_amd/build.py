@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libheget.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 # slowest first, so that the pool starts them at once
-SOURCES = ["me2_shapes_f32_meet8.hip", "me2_shapes_f32_meet7.hip",
+SOURCES = ["me2_shapes_f32_meet8.hip", "me2_shapes_sampled_meet8.hip", "me2_shapes_f32_meet7.hip",
            "me2_shapes_f32_lo.hip", "me2_shapes_f32_mid.hip", "me2_shapes_f32_hi.hip",
            "me2_shapes_f64_lo.hip", "me2_shapes_f64_mid.hip", "me2_shapes_f64_hi.hip",
            "me2_shapes_sampled.hip", "me2_batch.hip", "me2_registry.cpp", "mc_kernels.hip", "peak.hip", "helas_kernels.hip",

@@ -184,7 +184,7 @@ me2_kernel(const double *__restrict__ mom, int64_t ld, const int32_t *__restrict
     static_assert(PPL == 1 || PF == 0, "several points per lane only without prefetch");
     // LDS of one walk: the photon table of the top levels, or the held
     // currents of the meeting in the middle with LDS staging (PS = 4)
-    constexpr int kTab = N > MB ? kPhotonFields * N * 64 : PS == 4 ? meet_lds_values<N, H>() * 64 : 0;
+    constexpr int kTab = N > MB ? kPhotonFields * N * 64 : PS == 4 ? meet_lds_values<N, (H > 0 ? H : 1)>() * 64 : 0;
     __shared__ R tab_all[kTab > 0 ? WPB * PPL * kTab : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

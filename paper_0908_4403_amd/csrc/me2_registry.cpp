@@ -16,8 +16,8 @@ extern const Me2Variant kShapesF64Lo[], kShapesF64Mid[], kShapesF64Hi[];
 extern const int kShapesF32LoCount, kShapesF32MidCount, kShapesF32Meet7Count, kShapesF32Meet8Count,
     kShapesF32HiCount;
 extern const int kShapesF64LoCount, kShapesF64MidCount, kShapesF64HiCount;
-extern const Me2Variant kShapesSampled[];
-extern const int kShapesSampledCount;
+extern const Me2Variant kShapesSampled[], kShapesSampledMeet8[];
+extern const int kShapesSampledCount, kShapesSampledMeet8Count;
 
 static const std::vector<Me2Variant> &all_variants()
 {
@@ -54,6 +54,8 @@ const Me2Variant *me2_sampled(int prec, int n)
 {
     for (int i = 0; i < kShapesSampledCount; ++i)
         if (kShapesSampled[i].prec == prec && kShapesSampled[i].n == n) return &kShapesSampled[i];
+    for (int i = 0; i < kShapesSampledMeet8Count; ++i)
+        if (kShapesSampledMeet8[i].prec == prec && kShapesSampledMeet8[i].n == n) return &kShapesSampledMeet8[i];
     return nullptr;
 }
 

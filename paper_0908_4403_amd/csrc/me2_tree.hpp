@@ -696,24 +696,6 @@ __device__ __forceinline__ void row_propagator(const Prop<R> &P, const Half<R, H
     }
 }
 
-// Meet in the middle (shape field prefix_sets = 2; the whole tree unrolled,
-// photons in registers).  Every ordering of the n photons splits uniquely into
-// the set A of its first K photons (from the v-bar end) and the set B of the
-// other n - K, and its amplitude factorises at the propagator between them:
-// the v-bar-end current after A times the u-end row vector arriving from B.
-// Summed over the orderings of A and of B,
-//     sum over all orderings = sum over |A| = K of W(B) . J(A),
-//     J(Q) = d(q_Q) P(q_Q) sum_{j in Q} V_j J(Q \ j),  q_Q = -p2 + sum_Q k,
-//     R(C) = [sum_{c in C} R(C \ c) V_c] d(p1 - sum_C k) P(p1 - sum_C k),
-//     W(B) = sum_{b in B} R(B \ b) V_b,
-// with J(empty) the v-bar spinor and R(empty) V_c = (gamma_c, -1) the u-end
-// closing vertex.  This is the two-sided current reuse of the MadGraph program
-// (Appendix A.1) taken to the middle of every chain: each subset current is
-// formed once per helicity walk instead of once per ordering prefix.  The
-// C(n, K) contractions W(B) . J(A) are taken in the working precision and
-// each enters the FP64 ordering sum.  Levels up to K - 1 (v-bar end) and
-// n - K - 1 (u end) are held; level K and the row vectors W are formed at the
-// contraction that uses them.
 // Momentum base + SIGN * sum of the photons in MASK (in increasing photon order).
 template <int SIGN, unsigned MASK, typename R, int H, int N>
 __device__ __forceinline__ LMom<R> set_momentum(const LMom<R> &base, const Slots<R, H, N> &S)
@@ -794,9 +776,28 @@ __device__ __forceinline__ Chain<R, H> lds_get(const R *lds, int lane)
     return c;
 }
 
-// With kLds the v-bar-end currents of level K - 1 go to the wave's LDS region
-// `lds` (meet_lds_values<N, H>() values per lane) instead of registers, for
-// the shapes whose held currents would not fit in registers.
+// Meet in the middle (shape field prefix_sets = 2, 3, 4; the whole tree
+// unrolled, photons in registers).  Every ordering of the n photons splits
+// uniquely into the set A of its first K photons (from the v-bar end) and the
+// set B of the other n - K, and its amplitude factorises at the propagator
+// between them:
+// the v-bar-end current after A times the u-end row vector arriving from B.
+// Summed over the orderings of A and of B,
+//     sum over all orderings = sum over |A| = K of W(B) . J(A),
+//     J(Q) = d(q_Q) P(q_Q) sum_{j in Q} V_j J(Q \ j),  q_Q = -p2 + sum_Q k,
+//     R(C) = [sum_{c in C} R(C \ c) V_c] d(p1 - sum_C k) P(p1 - sum_C k),
+//     W(B) = sum_{b in B} R(B \ b) V_b,
+// with J(empty) the v-bar spinor and R(empty) V_c = (gamma_c, -1) the u-end
+// closing vertex.  This is the two-sided current reuse of the MadGraph program
+// (Appendix A.1) taken to the middle of every chain: each subset current is
+// formed once per helicity walk instead of once per ordering prefix.  The
+// C(n, K) contractions W(B) . J(A) are taken in the working precision and
+// each enters the FP64 ordering sum.  Levels up to K - 1 (v-bar end) and
+// n - K - 1 (u end) are held; level K and the row vectors W are formed at the
+// contraction that uses them.  With kLds the v-bar-end currents of level
+// K - 1 go to the wave's LDS region `lds` (meet_lds_values<N, H>() values per
+// lane) instead of registers, for the shapes whose held currents would not
+// fit in registers.
 template <typename R, int N, int K, int H, bool kLds = false>
 __device__ __forceinline__ void meet_sets(const Slots<R, H, N> &S, const LMom<R> &p1, const LMom<R> &q0,
                                           Acc<H> &acc, R *lds = nullptr, int lane = 0)
@@ -991,7 +992,16 @@ __device__ __forceinline__ double tree_one(const PointIn<R, N> &in, R *tab, int 
     Acc<1> acc;
     acc.re[0] = 0.0;
     acc.im[0] = 0.0;
-    if constexpr (N <= MB) {
+    if constexpr (PS >= 2) {
+        static_assert(N <= MB, "meeting in the middle keeps every photon in registers");
+        Slots<R, 1, N> S;
+#pragma unroll
+        for (int s = 0; s < N; ++s) {
+            S.k[s] = in.k[s];
+            S.v[s] = make_vert<R, 1>(in.k[s], cfg, s);
+        }
+        meet_sets<R, N, (N + 1) / 2, 1, PS == 4>(S, in.p1, in.q0, acc, tab, lane);
+    } else if constexpr (N <= MB) {
         Slots<R, 1, N> S;
 #pragma unroll
         for (int s = 0; s < N; ++s) {

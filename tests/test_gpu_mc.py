@@ -232,6 +232,7 @@ def test_back_to_back_calls_match_one_by_one(H):
     (5, "PP_TOY", dict(sqrt_s=14000.0, sqrt_shat_lo=150.0), 1500),
     (6, "FIXED_SHAT", dict(sqrt_s=1500.0), 300),
     (7, "FIXED_SHAT", dict(sqrt_s=1500.0), 200),
+    (8, "FIXED_SHAT", dict(sqrt_s=2000.0), 64),
 ])
 def test_helicity_sampling_matches_oracle_same_sample(H, orc, n, mode, extra, npoints):
     """One drawn helicity configuration per point (the paper's per-event
