@@ -837,8 +837,8 @@ __device__ __forceinline__ void meet_sets(const Slots<R, H, N> &S, const LMom<R>
                     vertex_half_add<R, H>(S.v[b], J[mask & ~(1u << b)], sl);
                 });
                 propagator_half<R, H>(P, sl, J[mask]);
-                if constexpr (kLds && L == K - 1) lds_put<R, N, H, mask>(lds, lane, J[mask]);
             }
+            if constexpr (kLds && L == K - 1) lds_put<R, N, H, mask>(lds, lane, J[mask]);
             if constexpr (kLds) __builtin_amdgcn_sched_barrier(0);
         });
     });
