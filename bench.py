@@ -359,6 +359,33 @@ def config_n8(H, torch, wl, reps):
     return out
 
 
+def sampling_leg(H, torch, n, base, reps):
+    """The paper's per-event helicities against the helicity sum on one
+    workload, FP32 amplitudes: sigma and its Monte-Carlo error per unit time.
+    One pass draws one configuration per point (estimator 2^(n+1)|M_h|^2);
+    the figure of merit of a mode is 1 / (err^2 * time per pass)."""
+    out = {}
+    for sampling, name in ((0, "summed"), (1, "sampled")):
+        cfg = H.Config(prec=H.FP32, helicity_sampling=sampling, **base)
+        buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
+        H.xsec_device(n, cfg, buf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            H.xsec_device(n, cfg, buf)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        r = H.result_from_bytes(buf.cpu().numpy())
+        out[name] = {"ms_per_pass": dt * 1e3, "sigma_fb": r["sigma_fb"], "sigma_err_fb": r["err_fb"],
+                     "rel_err": r["err_fb"] / r["sigma_fb"], "merit_per_s": 1.0 / (r["err_fb"] ** 2 * dt)}
+    out["sampled_merit_over_summed"] = out["sampled"]["merit_per_s"] / out["summed"]["merit_per_s"]
+    print(f"bench: n={n} helicity sampling {out['sampled']['ms_per_pass']:.3f} ms/pass "
+          f"(summed {out['summed']['ms_per_pass']:.3f}), rel err {out['sampled']['rel_err']:.2e} "
+          f"(summed {out['summed']['rel_err']:.2e}), merit ratio {out['sampled_merit_over_summed']:.2f}",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -372,6 +399,8 @@ def main():
                     help="skip the oracle leg (CPU baseline and per-point accuracy)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed n=2..7 batch")
     ap.add_argument("--no-n8", action="store_true", help="skip the n=8 workload (2^18 points at 2 TeV)")
+    ap.add_argument("--no-sampling", action="store_true",
+                    help="skip the helicity-sampling leg (sigma and its error per unit time)")
     ap.add_argument("--no-per-n", action="store_true", help="skip the per-n amplitude kernel timings")
     ap.add_argument("--per-n-list", default="2,3,4,5,6,7,8",
                     help="photon counts of the per-n section (comma-separated)")
@@ -438,6 +467,13 @@ def main():
     pern = None if args.no_per_n else per_n(H, torch, not args.no_tune,
                                             [int(x) for x in args.per_n_list.split(",")])
     n8 = None if args.no_n8 else config_n8(H, torch, workloads["uubar_8a_2TeV_2p18"], 1)
+    sampling = None
+    if not args.no_sampling:
+        w8 = workloads["uubar_8a_2TeV_2p18"]
+        base8 = dict(mode=w8["mode"], seed=w8["seed"], npoints=w8["npoints"], sqrt_s=w8["sqrt_s"],
+                     pt_min=w8["cuts"][0], eta_max=w8["cuts"][1], dr_min=w8["cuts"][2])
+        sampling = {args.workload: sampling_leg(H, torch, n, base, 50),
+                    "uubar_8a_2TeV_2p18": sampling_leg(H, torch, w8["n"], base8, 2)}
 
     cpu, accuracy = None, None
     if not args.no_cpu_baseline:
@@ -490,6 +526,7 @@ def main():
         "generated_points_per_s": wl["npoints"] / (ms32 * 1e-3),
         "tuned_shapes": tuned,
         "n8_workload": n8,
+        "helicity_sampling": sampling,
         "per_n": pern,
         "mixed_batch": mixed,
         "accuracy_vs_oracle": accuracy,
