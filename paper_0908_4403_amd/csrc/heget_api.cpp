@@ -481,19 +481,20 @@ double me2_flops_per_point(int n, int mb, int h, int cl, int ps)
         // depend on a variant photon are shared): v-bar-end currents of every
         // set of up to K = (n + 1) / 2 photons, u-end row vectors of every set
         // of up to n - K - 1, and per set A of K photons the row vector W of
-        // the other n - K and one contraction.  A node of L photons: momentum
-        // 4L (sum of its photons) + q^2 5 + 1/q^2 1 + scale 4; per distinct
-        // value one photon 11, else a vertex half 16, L - 1 vertex halves
-        // added 20 each and a propagator half 20.  W: 16 + 20 (n - K - 1) per
-        // distinct value; contraction 14 + 2 FP64 adds per helicity.  With
-        // ps = 2 the momentum parts are formed once per point (the compiler
-        // takes them out of the loop over walks), otherwise once per walk.
+        // the other n - K and one contraction.  A node: momentum 4 (its set's
+        // sum is a subset's sum plus one photon, which the compiler shares) +
+        // q^2 5 + 1/q^2 1 + scale 4; per distinct value one photon 11, else a
+        // vertex half 16, L - 1 vertex halves added 20 each and a propagator
+        // half 20 (L photons).  W: 16 + 20 (n - K - 1) per distinct value;
+        // contraction 14 + 2 FP64 adds per helicity.  With ps = 2 the
+        // momentum parts are formed once per point (the compiler takes them
+        // out of the loop over walks), otherwise once per walk.
         const int K = (n + 1) / 2, ku = n - K;
         double momenta = 0.0;
         auto node = [&](unsigned set) {
             const int L = __builtin_popcount(set);
             const double per = L == 1 ? 11.0 : 36.0 + 20.0 * (L - 1);
-            momenta += 4.0 * L + 10.0;
+            momenta += 14.0;
             return per * w.var_count(set);
         };
         w.total += 4.0 * n;

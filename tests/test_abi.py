@@ -170,8 +170,8 @@ def _flops_meet(n, h, ps):
     K = (n + 1) / 2, the v-bar-end subset currents of every set of 1 .. K - 1
     photons, the u-end ones of every set of 1 .. n - K - 1, and per set of K
     photons its current, the row vector of the other n - K photons and one
-    contraction.  A node of m photons: momentum 4m + 10 (once per point for
-    ps = 2, once per walk otherwise); per helicity 11 for one photon, else
+    contraction.  A node of m photons: momentum 14 (once per point for ps = 2,
+    once per walk otherwise); per helicity 11 for one photon, else
     36 + 20 (m - 1).  Row vector: 16 + 20 (n - K - 1) per helicity;
     contraction 16 per helicity; vertex blocks 4 per photon."""
     import math
@@ -185,7 +185,7 @@ def _flops_meet(n, h, ps):
     sizes = list(range(1, K)) + list(range(1, ku)) + [K]
     walk = 4 * n + 4 * h + sum(math.comb(n, m) * per(m) for m in sizes)
     walk += math.comb(n, K) * ((16 + 20 * (ku - 1)) * h + 16 * h)
-    momenta = sum(math.comb(n, m) * (4 * m + 10) for m in sizes)
+    momenta = sum(math.comb(n, m) * 14 for m in sizes)
     return walk * walks + momenta * (1 if ps == 2 else walks)
 
 
