@@ -131,15 +131,15 @@ def _golden_n8(orc, count):
 def test_every_compiled_shape_matches_oracle(H, orc, n):
     """Each unrolled depth / helicities-per-walk / waves-per-block shape the
     autotuner may pick gives the oracle's |M|^2 (FP64 shapes to 1e-12, FP32 at
-    the median / 99.9th-percentile bars).  n = 7 and 8 run on 300 points (four
-    full tiles and a ragged fifth), so waves of a four-wave block each hold
-    different points and the per-lane LDS photon tables are exercised."""
-    count = {2: 200, 3: 130, 4: 70, 5: 67, 6: 20, 7: 300, 8: 300}[n]
+    the median / 99.9th-percentile bars).  n = 5..8 run on 200-300 points
+    (several full tiles and a ragged last one), so waves of a four-wave block
+    each hold different points and the per-lane LDS tables are exercised."""
+    count = {2: 200, 3: 130, 4: 70, 5: 300, 6: 200, 7: 300, 8: 300}[n]
     if n == 8:
         ev, ref = _golden_n8(orc, count)
     else:
         ev = cut_events(orc, n, 1200.0, 300 + n, count)
-        ref = (orc.me2_subsets_batch(ev) if n >= 7 else orc.me2_batch(ev))[0]
+        ref = (orc.me2_subsets_batch(ev) if n >= 6 else orc.me2_batch(ev))[0]
     try:
         for prec in (H.FP64, H.FP32):
             for shape in H.kernel_shapes(n, prec):
