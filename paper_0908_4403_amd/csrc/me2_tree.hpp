@@ -738,6 +738,24 @@ constexpr int binomial(int n, int k)
     return r;
 }
 
+// The i-th mask with k bits set, in increasing order (Gosper's rule).
+constexpr uint32_t nth_subset(int k, int i)
+{
+    uint32_t v = (1u << k) - 1u;
+    for (int t = 0; t < i; ++t) {
+        const uint32_t c = v | (v - 1u);
+        v = (c + 1u) | (((~c & (c + 1u)) - 1u) >> (__builtin_ctz(v) + 1));
+    }
+    return v;
+}
+
+// Index of the j-th set bit of m (j = 0: the lowest).
+constexpr int nth_bit(uint32_t m, int j)
+{
+    for (int t = 0; t < j; ++t) m &= m - 1u;
+    return __builtin_ctz(m);
+}
+
 // LDS values per lane of meet_sets with LDS staging: the v-bar-end currents of
 // level K - 1, 4 H components each.
 template <int N, int H>
@@ -807,12 +825,6 @@ __device__ __forceinline__ void meet_sets(const Slots<R, H, N> &S, const LMom<R>
     constexpr int kU = N - K;
     Chain<R, H> J[1 << N];
     Row<R, H> Rw[1 << N];
-    // current of set M of level K - 1 (registers or LDS)
-    auto held = [&](auto mi) -> Chain<R, H> {
-        constexpr uint32_t M = decltype(mi)::value;
-        if constexpr (kLds && __builtin_popcount(M) == K - 1) return lds_get<R, N, H, M>(lds, lane);
-        else return J[M];
-    };
     // v-bar end, level by level (a level's currents die once the next is formed)
     static_for<1, K>([&](auto li) {
         constexpr int L = decltype(li)::value;
@@ -870,15 +882,15 @@ __device__ __forceinline__ void meet_sets(const Slots<R, H, N> &S, const LMom<R>
             if constexpr (kLds) __builtin_amdgcn_sched_barrier(0);
         });
     });
-    // the contractions, one per set A of K photons
-    for_each_subset<N, K>([&](auto mi) {
-        constexpr uint32_t A = decltype(mi)::value;
+    // the contraction of set A, given the currents of A minus each of its
+    // photons (hA[j]: A without its j-th photon)
+    auto contract = [&](auto ai, const Chain<R, H> (&hA)[K]) {
+        constexpr uint32_t A = decltype(ai)::value;
         constexpr uint32_t B = kAll & ~A;
-        constexpr int low = __builtin_ctz(A);
-        Half<R, H> sl = vertex_half<R, H>(S.v[low], held(std::integral_constant<uint32_t, (A & ~(1u << low))>{}));
-        for_each_bit<(A & (A - 1u))>([&](auto bit) {
-            constexpr int b = decltype(bit)::value;
-            vertex_half_add<R, H>(S.v[b], held(std::integral_constant<uint32_t, (A & ~(1u << b))>{}), sl);
+        Half<R, H> sl = vertex_half<R, H>(S.v[nth_bit(A, 0)], hA[0]);
+        static_for<1, K>([&](auto ji) {
+            constexpr int j = decltype(ji)::value;
+            vertex_half_add<R, H>(S.v[nth_bit(A, j)], hA[j], sl);
         });
         Chain<R, H> ja;
         propagator_half<R, H>(prop_at<R>(set_momentum<1, A>(q0, S)), sl, ja);
@@ -901,11 +913,46 @@ __device__ __forceinline__ void meet_sets(const Slots<R, H, N> &S, const LMom<R>
             acc.re[h] += static_cast<double>(ar);
             acc.im[h] += static_cast<double>(ai);
         }
-        // with LDS staging, no instruction moves across a node or contraction
-        // (the scheduler would otherwise hoist later nodes' loads and products
-        // and hold their values together)
-        if constexpr (kLds) __builtin_amdgcn_sched_barrier(0);
-    });
+    };
+    // the contractions, one per set A of K photons in increasing order
+    constexpr int kSets = binomial(N, K);
+    if constexpr (kLds) {
+        // the held currents of the next set are read from LDS before the
+        // current contraction, so the reads overlap its arithmetic; no
+        // instruction moves across a contraction (the scheduler would
+        // otherwise hoist later contractions' reads and products and hold
+        // their values together)
+        auto load_set = [&](auto ai, Chain<R, H>(&dst)[K]) {
+            constexpr uint32_t A = nth_subset(K, decltype(ai)::value);
+            static_for<0, K>([&](auto ji) {
+                constexpr int j = decltype(ji)::value;
+                dst[j] = lds_get<R, N, H, (A & ~(1u << nth_bit(A, j)))>(lds, lane);
+            });
+        };
+        Chain<R, H> cur[K];
+        load_set(std::integral_constant<int, 0>{}, cur);
+        static_for<0, kSets>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            Chain<R, H> nxt[K];
+            if constexpr (i + 1 < kSets) load_set(std::integral_constant<int, i + 1>{}, nxt);
+            contract(std::integral_constant<uint32_t, nth_subset(K, i)>{}, cur);
+            if constexpr (i + 1 < kSets) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) cur[j] = nxt[j];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    } else {
+        static_for<0, kSets>([&](auto ii) {
+            constexpr uint32_t A = nth_subset(K, decltype(ii)::value);
+            Chain<R, H> hA[K];
+            static_for<0, K>([&](auto ji) {
+                constexpr int j = decltype(ji)::value;
+                hA[j] = J[A & ~(1u << nth_bit(A, j))];
+            });
+            contract(std::integral_constant<uint32_t, A>{}, hA);
+        });
+    }
 }
 
 // Per-point inputs after the FP64 set-up.
