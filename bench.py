@@ -16,7 +16,12 @@ of the whole step.  The roofline object is for the amplitude kernel: its
 algorithmic flops (heget_me2_flops, counted on the schedule actually run)
 times the points per launch, over its average launch time measured with HIP
 events on the launch stream.  cpu_baseline times the FP64 CPU oracle
-(brute-force ordering sum) on a bounded sample of the same points.
+(brute-force ordering sum) on a bounded sample of the same points.  Beside
+the headline line: the amplitude kernels alone for n = 2..8 (per_n), the
+n = 8 workload (2^18 points at 2 TeV, FP32 and FP64), the mixed n = 2..7
+batch, the paper's per-event helicity sampling against the helicity sum
+(sigma and its error per unit time), and the per-point error against the
+oracle.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 """
