@@ -7,7 +7,7 @@
 namespace heget {
 
 extern const Me2Variant kShapesF32Meet7[] = {
-    variant<float, 7, 7, 2, 2, 1, 0, 0, 1, 3>(), variant<float, 7, 7, 1, 2, 1, 0, 0, 1, 3>(),
+    variant<float, 7, 7, 4, 2, 1, 0, 0, 1, 3>(), variant<float, 7, 7, 2, 2, 1, 0, 0, 1, 3>(),
 };
 extern const int kShapesF32Meet7Count = sizeof(kShapesF32Meet7) / sizeof(Me2Variant);
 
